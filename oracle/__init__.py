@@ -82,6 +82,8 @@ def _load():
     llp = ctypes.POINTER(ctypes.c_longlong)
     cp = ctypes.POINTER(OCfg)
     jp = ctypes.POINTER(OJet)
+    lib.oracle_threads.argtypes = []
+    lib.oracle_threads.restype = ctypes.c_int
     lib.oracle_weno7.argtypes = [dp, ctypes.c_int, ctypes.c_double, ctypes.c_int]
     lib.oracle_weno7.restype = ctypes.c_double
     lib.oracle_prim_to_cons.argtypes = [cp, dp, dp]
@@ -170,6 +172,11 @@ def _jets(jets):
     for i, j in enumerate(jets):
         arr[i] = j.c() if isinstance(j, Jet) else j
     return arr, len(jets)
+
+
+def threads() -> int:
+    """OpenMP threads the oracle runs on."""
+    return int(_load().oracle_threads())
 
 
 def weno7(a, scheme: str = "z", eps: float = 1e-6, p: int = 2) -> float:

@@ -35,6 +35,10 @@
 #include <cstring>
 #include <vector>
 
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
 namespace {
 
 using cplx = std::complex<double>;
@@ -177,8 +181,8 @@ S temperature(const S& e, const ocfg& c) {
 // a[0..6] = a_{i-3}..a_{i+3} (point values treated as cell averages).
 // Candidate values q_k on the four 4-point stencils, ideal weights
 // (1, 12, 18, 4)/35, smoothness indicators from the Jiang-Shu integral
-// definition (integer forms / 240), and WENO-Z (tau = |b0 + 3b1 - 3b2 - b3|),
-// Jiang-Shu or linear weights.
+// definition, and WENO-Z (tau = |b0 + 3b1 - 3b2 - b3|), Jiang-Shu or linear
+// weights.
 template <class S>
 S weno7_left(const S* a, int scheme, double eps, int pz) {
   const S& m3 = a[0];
@@ -201,19 +205,29 @@ S weno7_left(const S* a, int scheme, double eps, int pz) {
     return d[0] * q[0] + d[1] * q[1] + d[2] * q[2] + d[3] * q[3];
   }
 
+  // Smoothness indicators, Jiang-Shu definition: beta_k = sum_{l=1..3}
+  // int_{cell i} (d^l p_k / dx^l)^2 dx (unit cell width), p_k the cubic whose
+  // cell averages are the four stencil values.  With p_k = c0 + c1 x + c2 x^2
+  // + c3 x^3 about the centre of cell i the integral is
+  //   (c1 + c3/4)^2 + 13/3 c2^2 + 781/20 c3^2,
+  // and c1..c3 follow from the differences D1, D2, D3 of the stencil values:
+  //   c3 = D3/6,  c2 = D2/2 + g_k D3,  c1 = D1 + h_k D2 + m_k D3.
+  // Written with differences, beta vanishes exactly on flat stencils.
+  const double gk[4] = {1.0, 0.5, 0.0, -0.5};
+  const double hk[4] = {2.5, 1.5, 0.5, -0.5};
+  const double mk[4] = {43.0 / 24.0, 7.0 / 24.0, -5.0 / 24.0, 7.0 / 24.0};
   S b[4];
-  b[0] = (547.0 * m3 * m3 - 3882.0 * m3 * m2 + 4642.0 * m3 * m1 - 1854.0 * m3 * z0 +
-          7043.0 * m2 * m2 - 17246.0 * m2 * m1 + 7042.0 * m2 * z0 +
-          11003.0 * m1 * m1 - 9402.0 * m1 * z0 + 2107.0 * z0 * z0) / 240.0;
-  b[1] = (267.0 * m2 * m2 - 1642.0 * m2 * m1 + 1602.0 * m2 * z0 - 494.0 * m2 * p1 +
-          2843.0 * m1 * m1 - 5966.0 * m1 * z0 + 1922.0 * m1 * p1 +
-          3443.0 * z0 * z0 - 2522.0 * z0 * p1 + 547.0 * p1 * p1) / 240.0;
-  b[2] = (547.0 * m1 * m1 - 2522.0 * m1 * z0 + 1922.0 * m1 * p1 - 494.0 * m1 * p2 +
-          3443.0 * z0 * z0 - 5966.0 * z0 * p1 + 1602.0 * z0 * p2 +
-          2843.0 * p1 * p1 - 1642.0 * p1 * p2 + 267.0 * p2 * p2) / 240.0;
-  b[3] = (2107.0 * z0 * z0 - 9402.0 * z0 * p1 + 7042.0 * z0 * p2 - 1854.0 * z0 * p3 +
-          11003.0 * p1 * p1 - 17246.0 * p1 * p2 + 4642.0 * p1 * p3 +
-          7043.0 * p2 * p2 - 3882.0 * p2 * p3 + 547.0 * p3 * p3) / 240.0;
+  for (int k = 0; k < 4; ++k) {
+    const S* f = a + k;  // a_{i-3+k} .. a_{i+k}
+    S d1a = f[1] - f[0], d1b = f[2] - f[1], d1c = f[3] - f[2];
+    S d2a = d1b - d1a, d2b = d1c - d1b;
+    S D1 = d1a, D2 = d2a, D3 = d2b - d2a;
+    S c3 = D3 / 6.0;
+    S c2 = D2 / 2.0 + gk[k] * D3;
+    S c1 = D1 + hk[k] * D2 + mk[k] * D3;
+    S t = c1 + c3 / 4.0;
+    b[k] = t * t + (13.0 / 3.0) * c2 * c2 + (781.0 / 20.0) * c3 * c3;
+  }
 
   S alpha[4];
   if (scheme == 1) {
@@ -573,6 +587,15 @@ bool valid(const ocfg* c) {
 }  // namespace
 
 extern "C" {
+
+// Number of OpenMP threads the oracle's loops use.
+int oracle_threads(void) {
+#ifdef _OPENMP
+  return omp_get_max_threads();
+#else
+  return 1;
+#endif
+}
 
 // WENO7 left-biased reconstruction of seven values (unit tests).
 double oracle_weno7(const double* a, int scheme, double eps, int p) {

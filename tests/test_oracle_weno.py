@@ -175,3 +175,19 @@ def test_weno_z_converges_at_seventh_order():
         errs.append(abs(O.weno7(avg, "z") - exact))
     orders = [np.log2(errs[i] / errs[i + 1]) for i in range(len(errs) - 1)]
     assert min(orders) > 6.5, (errs, orders)
+
+
+@pytest.mark.parametrize("scheme", ["js", "z"])
+def test_flat_stencils_are_well_conditioned(scheme):
+    # Outflow ghost cells make some stencils exactly flat.  There the
+    # smoothness indicators must vanish exactly (evaluated from differences),
+    # not leave rounding residue comparable with epsilon: the result must
+    # agree with the 40-digit evaluation of the definition to ~1e-15.
+    rng = np.random.default_rng(17)
+    for trial in range(30):
+        c = rng.uniform(0.5, 5.0) * rng.choice([-1, 1])
+        tail = c + rng.normal(size=3) * rng.uniform(1e-3, 0.3)
+        for vals in (np.r_[[c] * 4, tail], np.r_[tail[::-1], [c] * 4], np.r_[[c] * 5, tail[:2]]):
+            got = O.weno7(vals, scheme)
+            ref = ref_weno(vals, scheme)
+            assert abs(got - ref) <= 1.5e-15 * max(1.0, np.abs(vals).max()), (trial, vals, got - ref)
