@@ -1,0 +1,162 @@
+#!/usr/bin/env python3
+"""Throughput of the jet + ideal-hydro SSP-RK3 step on one MI355X.
+
+A step is one full SSP-RK3 step (three stages of WENO7 x/y/z faces, jet
+source, RK combine) plus the FP64 conservation sums, over the paper's shape:
+256^3 cells, dx = 0.1 fm, dt = 0.02 fm/c, p = e/3, one jet (synthetic,
+seeded inputs; see paper_1511_02137_amd/workloads.py).  The inputs are
+resident in HBM before the timed region starts.
+
+Prints one JSON line: whole-job cell-updates/s (cells x stages / s), the
+roofline of the dominant kernel from HIP events recorded around every
+launch on the launch stream over the timed region, and the CPU oracle timed
+on a bounded slab of the same workload.
+
+    python bench.py [--steps K] [--warmup W] [--precision f64|f32] [--n 256]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "cell-updates/s per RK3 stage at 256^3 (% of roofline); adjoint/forward time"
+
+# Algorithmic flops per cell and kernel (adds and multiplies 1, fma 2,
+# divide and square root 1), minimal form of the scheme:
+#   one WENO7-Z reconstruction: candidates 28, smoothness 92, tau 4,
+#   weights 20, sum 3, combination 7, normalisation 1 = 155;
+#   per face 10 reconstructions (5 fields x 2 splits) = 1550;
+#   flux and Lax-Friedrichs split per cell and axis 25;
+#   divergence 10 per axis; conserved->primitive 25 (counted once, x);
+#   RK combine 15 (z).
+FLOPS_PER_CELL = {
+    "xface": 1550 + 25 + 10 + 25,
+    "ymarch": 1550 + 25 + 10,
+    "zmarch": 1550 + 25 + 10 + 15,
+}
+FLOPS_PER_CELL_UPDATE = sum(FLOPS_PER_CELL.values())  # 4795
+PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3}  # MI355X vector FP64 / FP32 (packed)
+
+
+def cpu_baseline(w, target_s: float):
+    """The oracle, one RK3 step on a centred z-slab of the same workload."""
+    import numpy as np
+    import oracle as O
+    nz = w.n[2]
+
+    def run_slab(planes):
+        z0 = (nz - planes) // 2
+        prim = np.ascontiguousarray(w.prim0[:, z0:z0 + planes])
+        pb = O.Problem(n=(w.n[0], w.n[1], planes), dx=w.dx, t0=w.t0, dt=w.dt, bc=w.bc)
+        U = O.prim_to_cons(pb, prim)
+        jets = [O.Jet(**j.__dict__) for j in w.jets]
+        t = time.perf_counter()
+        O.run(pb, U, 1, jets)
+        return time.perf_counter() - t
+
+    planes = min(nz, 8)
+    t = run_slab(planes)
+    if t < 0.5 * target_s and planes < nz:
+        planes = min(nz, max(planes + 1, int(planes * target_s / max(t, 1e-3))))
+        t = run_slab(planes)
+    cells = w.n[0] * w.n[1] * planes
+    return {
+        "value": cells * 3 / t,
+        "unit": "cell-updates/s",
+        "cores": O.threads(),
+        "kind": "oracle",
+        "sample": "one RK3 step (3 stages) of the central %dx%dx%d z-slab of the %s workload, outflow, "
+                  "%.1f s wall" % (w.n[0], w.n[1], planes, w.name, t),
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--precision", choices=["f64", "f32"], default="f64")
+    ap.add_argument("--n", type=int, default=256, help="cells per axis")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target length of the CPU oracle sample")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU: the stage update is built and measured on a single MI355X "
+              "(multi-GPU domain decomposition is designed, not built). Run with --gpus 1.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1511_02137_amd import hydro as H
+    from paper_1511_02137_amd import workloads as W
+
+    w = W.paper_event(2, n=(args.n,) * 3)
+    h = H.from_workload(w, precision=args.precision)
+    nc = w.n[0] * w.n[1] * w.n[2]
+
+    h.step(args.warmup)
+    torch.cuda.synchronize()
+
+    h.profile(True)
+    start = torch.cuda.Event(enable_timing=True)
+    stop = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    start.record()
+    h.step(args.steps)
+    stop.record()
+    torch.cuda.synchronize()
+    ms = start.elapsed_time(stop)
+    prof = h.profile_read()
+    h.profile(False)
+    fix = h.fixups()
+
+    value = nc * 3 * args.steps / (ms * 1e-3)
+    per_kernel = {k: {"ms_per_launch": (t / n if n else 0.0), "launches": n} for k, (t, n) in prof.items()}
+    dom = max(FLOPS_PER_CELL, key=lambda k: prof[k][0])
+    t_launch = prof[dom][0] / prof[dom][1]
+    achieved = FLOPS_PER_CELL[dom] * nc / (t_launch * 1e-3) / 1e12
+    peak = PEAK_TFLOPS[args.precision]
+    roofline = {"bound": "alu", "kernel": dom, "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
+                "frac": achieved / peak, "traffic": None,
+                "flops_per_cell": FLOPS_PER_CELL[dom]}
+    step_frac = FLOPS_PER_CELL_UPDATE * value / 1e12 / peak
+
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "cell-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": args.precision,
+        "data": "synthetic",
+        "config": {"workload": "%s: %d^3 cells, dx 0.1 fm, dt 0.02 fm/c, p = e/3, WENO7-Z + LF split, "
+                               "SSP-RK3, 1 jet (NGP), outflow" % (w.name, args.n),
+                   "grid": list(w.n), "precision": args.precision, "jets": len(w.jets)},
+        "roofline": roofline,
+        "step_alu_frac": step_frac,
+        "flops_per_cell_update": FLOPS_PER_CELL_UPDATE,
+        "kernels": per_kernel,
+        "fixups": fix,
+    }
+    print("timed %d steps: %.3f ms/step, %.3e cell-updates/s" % (args.steps, ms / args.steps, value),
+          file=sys.stderr, flush=True)
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

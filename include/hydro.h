@@ -1,0 +1,192 @@
+/* hydro.h -- C ABI of libhydro: the per-stage update of (3+1)D ideal
+ * relativistic hydrodynamics with a jet source on a Cartesian grid, for
+ * AMD MI355X (gfx950).
+ *
+ * The problem is the one of Marcinkowski et al., "Jet-induced modifications
+ * of the characteristic of the bulk nuclear matter" (arXiv:1511.02137),
+ * section "Simulation setup":
+ *   Eq. (1)  d_mu T^{mu nu} = d_mu((e+p) u^mu u^nu - p g^{mu nu}) = S^nu, with
+ *            the conserved variables energy, momentum and charge density;
+ *   Eq. (2)  S^nu(x) = sum_i (-dE/dt, -dM/dt) delta^3(x - x_i(t));
+ *   Eq. (3)  -dE/dx = kappa_rad (C_R/C_F) T^3 x + kappa_coll (C_R/C_F) T^2;
+ *   7th-order WENO in space, third-order Runge-Kutta in time;
+ *   EOS p = e/3 (Fig. 3 caption); dx = 0.1 fm, dt = 0.02 fm/c, 256^3 grid.
+ *
+ * Units: lengths fm, times fm/c, e / E / M GeV fm^-3, n / N fm^-3, T GeV,
+ * jet energies GeV.  T follows from e = g pi^2/30 T^4/(hbar c)^3.
+ *
+ * Conventions for every entry point:
+ *   - The state U is caller-owned device memory laid out as five fields
+ *     [E, Mx, My, Mz, N][nz][ny][nx], x fastest (structure of arrays), with
+ *     E = T^00, M_i = T^0i, N = n u^0; element type double (HYDRO_F64) or
+ *     float (HYDRO_F32).  Cells are centred: x_i = (i - (nx-1)/2) dx.
+ *   - Large buffers (U, primitives, adjoint fields, workspace) belong to the
+ *     caller.  The library owns only the opaque context: configuration, jet
+ *     table and a few small device scalars (jet energies, ledger, sums).
+ *   - Calls are asynchronous on `stream` (a hipStream_t; NULL = the default
+ *     stream) unless stated otherwise.
+ *   - Every function returns a hydro_status.  Argument errors return
+ *     HYDRO_EINVAL before any side effect; HIP errors return HYDRO_EDEVICE
+ *     and hydro_last_error() gives the HIP error text.  Nothing aborts or
+ *     throws across the ABI.
+ */
+#ifndef HYDRO_H
+#define HYDRO_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  HYDRO_OK = 0,
+  HYDRO_EINVAL = -1,    /* bad argument or configuration */
+  HYDRO_ENOMEM = -2,    /* a device allocation of the library failed */
+  HYDRO_EDEVICE = -3,   /* a HIP call failed */
+  HYDRO_ENONPHYS = -4,  /* strict mode: a non-admissible cell was met */
+  HYDRO_ESTATE = -5     /* call not valid in the context's current state */
+} hydro_status;
+
+typedef enum {
+  HYDRO_F64 = 0,  /* all arithmetic in FP64 */
+  HYDRO_F32 = 1   /* fields and flux arithmetic FP32; conserved->primitive
+                     recovery, conservation sums, jet source and parameter
+                     gradients in FP64 */
+} hydro_precision;
+
+typedef enum { HYDRO_BC_OUTFLOW = 0, HYDRO_BC_PERIODIC = 1 } hydro_bc;
+
+/* Discretisation of the delta function of Eq. (2). */
+typedef enum {
+  HYDRO_DEP_NGP = 0,   /* the cell that holds the jet; ties to the upper cell */
+  HYDRO_DEP_GAUSS = 1  /* separable Gaussian, sigma = dx, over 7^3 cells */
+} hydro_deposit;
+
+/* Nonlinear weights of the 7th-order WENO reconstruction. */
+typedef enum { HYDRO_WENO_Z = 0, HYDRO_WENO_JS = 1, HYDRO_WENO_LINEAR = 2 } hydro_weno;
+
+typedef struct {
+  int32_t n[3];        /* cells along x, y, z >= 1; n[0] <= 810 (FP64) or 1024 (FP32) */
+  double dx[3];        /* cell widths [fm], > 0 */
+  double t0;           /* initial time [fm/c] */
+  double dt;           /* time step [fm/c], > 0 */
+  int32_t bc[3];       /* hydro_bc per axis; outflow = zero-gradient ghost cells */
+  int32_t precision;   /* hydro_precision */
+  int32_t weno;        /* hydro_weno (default HYDRO_WENO_Z) */
+  int32_t deposit;     /* hydro_deposit */
+  double weno_eps;     /* epsilon of the weights, (GeV/fm^3)^2 scale; 1e-6 */
+  int32_t weno_p;      /* exponent of the WENO-Z weights; 2 (only 2 is built) */
+  int32_t strict;      /* 1: hydro_sums reports HYDRO_ENONPHYS after fix-ups */
+  double eos_dof;      /* g of e = g pi^2/30 T^4/(hbar c)^3; 47.5 */
+  double hbarc;        /* hbar c [GeV fm]; 0.1973269804 */
+} hydro_config;
+
+/* One jet (Eq. 2, 3): a straight line at the speed of light from x0 in
+ * direction dir (unit vector), created at t_start.  It deposits energy and
+ * momentum dir * energy at the rate P = kappa_coll (C_R/C_F) T^2/(hbar c) +
+ * kappa_rad (C_R/C_F) T^3 l/(hbar c)^2 [GeV/fm], l = t - t_start the path
+ * length, T the local temperature of the stage input.  It deposits while its
+ * energy (initially E0, decreased by what it deposits) is positive. */
+typedef struct {
+  double x0[3];
+  double dir[3];
+  double E0;
+  double t_start;
+  double kappa_rad;
+  double kappa_coll;
+  double cr_over_cf;
+} hydro_jet;
+
+typedef struct hydro_ctx hydro_ctx;
+
+/* Fill *cfg with the defaults: the paper's 256^3 shape, dx = 0.1 fm,
+ * dt = 0.02 fm/c, t0 = 1 fm/c, outflow, FP64, WENO-Z, NGP deposit. */
+void hydro_default_config(hydro_config* cfg);
+
+/* Bytes of caller-provided device workspace that hydro_init needs for cfg:
+ * two stage states and one flux-divergence field (15 words per cell) plus
+ * reduction partials.  adjoint_k > 0 adds room for the 3*adjoint_k stage
+ * states one hydro_adjoint_step of adjoint_k steps recomputes and for the
+ * adjoint fields.  Returns 0 for an invalid cfg. */
+size_t hydro_workspace_bytes(const hydro_config* cfg, int adjoint_k);
+
+/* Create a context and set U from primitive fields.
+ *   prim0     [5][nz][ny][nx] double: e, vx, vy, vz, n; host or device
+ *             memory (detected); |v| < 1, e > 0.  May be NULL: U is then
+ *             taken as already initialised by the caller.
+ *   U         device, [5][nz][ny][nx] of the precision's type; written.
+ *   workspace device, >= hydro_workspace_bytes(cfg, adjoint_k) bytes,
+ *             256-byte aligned; owned by the caller, used until destroy.
+ *   ws_bytes  its size.
+ * The conversion is E = (e+p) gamma^2 - p, M = (e+p) gamma^2 v, N = n gamma
+ * with p = e/3.  The context starts at step 0, t = t0, with no jets. */
+int hydro_init(const hydro_config* cfg, const double* prim0, void* U, void* workspace,
+               size_t ws_bytes, void* stream, hydro_ctx** out);
+
+/* Append a jet; *jet_id (may be NULL) receives its index.  Synchronous. */
+int hydro_add_jet(hydro_ctx* ctx, const hydro_jet* jet, int* jet_id);
+
+/* Advance U (in place) by nsteps Shu-Osher SSP-RK3 steps:
+ *   U1 = U + dt L(U);  U2 = 3/4 U + 1/4 (U1 + dt L(U1));
+ *   U  = 1/3 U + 2/3 (U2 + dt L(U2)),
+ * stage times t_n, t_n + dt, t_n + dt/2, with t_n = t0 + n dt.  L = D + S is
+ * the flux divergence of the component-wise WENO7 reconstruction of the
+ * Lax-Friedrichs split fluxes F+- = (f +- U)/2 (alpha = 1) plus the jet
+ * source.  After each step the jet energies and the deposited-energy ledger
+ * advance by dt (P1/6 + P2/6 + 2 P3/3) and the FP64 sums of U dV are taken. */
+int hydro_rk3_step(hydro_ctx* ctx, void* U, int nsteps, void* stream);
+
+/* Right-hand side of one stage, L(U) = D(U) + S(U) at time t, into L
+ * (device, same layout and type as U, not aliasing U).  Jets deposit with
+ * their current energies; E_jet and the ledger are not advanced. */
+int hydro_rhs(hydro_ctx* ctx, const void* U, double t, void* L, void* stream);
+
+/* Primitive fields of U: prim [6][nz][ny][nx] of U's type: e, vx, vy, vz,
+ * n, T (device).  Recovery in FP64 with p = e/3. */
+int hydro_primitives(hydro_ctx* ctx, const void* U, void* prim, void* stream);
+
+/* Synchronous: out[0..4] = sum over cells of E, Mx, My, Mz, N times dV
+ * (FP64, fixed reduction order), out[5] = deposited-energy ledger.
+ * Returns HYDRO_ENONPHYS in strict mode after a fix-up. */
+int hydro_sums(hydro_ctx* ctx, const void* U, double out[6], void* stream);
+
+/* Synchronous: time, step index and the jets' remaining energies. */
+int hydro_get_state(hydro_ctx* ctx, double* t, int64_t* step, double* E_jet, int n_jet);
+int hydro_set_state(hydro_ctx* ctx, int64_t step, const double* E_jet, int n_jet, double ledger);
+
+/* Synchronous: number of conserved->primitive fix-ups so far. */
+int hydro_diag(hydro_ctx* ctx, int64_t* fixups);
+
+/* Kernel classes of a step, for hydro_profile_read. */
+typedef enum {
+  HYDRO_K_XFACE = 0,   /* x-faces of every row */
+  HYDRO_K_XBOUND = 1,  /* right boundary x-face of every row (outflow) */
+  HYDRO_K_YMARCH = 2,  /* y-faces (march along y) */
+  HYDRO_K_JET = 3,     /* jet source */
+  HYDRO_K_ZMARCH = 4,  /* z-faces (march along z) and the RK combine */
+  HYDRO_K_SUMS = 5,    /* FP64 conservation sums */
+  HYDRO_NK = 6
+} hydro_kernel_class;
+
+/* Diagnostics: with enable != 0, every later launch of hydro_rk3_step is
+ * bracketed by HIP events recorded on its stream.  Not for use under graph
+ * capture. */
+int hydro_profile(hydro_ctx* ctx, int enable);
+
+/* Synchronous: total milliseconds and launch counts per kernel class since
+ * the last read (arrays of nk entries, nk <= HYDRO_NK); then clears. */
+int hydro_profile_read(hydro_ctx* ctx, double* ms, int64_t* launches, int nk);
+
+/* Text of the last error on ctx (or of the last failed hydro_init if ctx is
+ * NULL).  Valid until the next call on ctx. */
+const char* hydro_last_error(const hydro_ctx* ctx);
+
+void hydro_destroy(hydro_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HYDRO_H */

@@ -1,0 +1,542 @@
+// hydro_api.hip -- host side of libhydro: the C ABI of include/hydro.h.
+//
+// The context keeps the configuration, the jet table and a small block of
+// device scalars; all large buffers are the caller's.  A step is a fixed
+// sequence of launches on the caller's stream with no host synchronisation,
+// so a caller may capture it in a HIP graph.
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "hydro.h"
+#include "hydro_internal.hpp"
+
+namespace hydro {
+template <class R>
+hipError_t launch_face_kernel(int kernel, const StageArgs<R>& a, int scheme, int seg, hipStream_t st);
+template <class R>
+hipError_t launch_jet(const JetArgs& a, hipStream_t st);
+template <class R>
+hipError_t launch_sums(const R* U, long long nc, double dV, double* part, DevScalars* s, hipStream_t st);
+template <class R>
+hipError_t launch_prim_to_cons(const double* prim, R* U, long long nc, hipStream_t st);
+template <class R>
+hipError_t launch_primitives(const R* U, R* prim, long long nc, double g, double hc, unsigned long long* fixups,
+                             hipStream_t st);
+}  // namespace hydro
+
+using namespace hydro;
+
+struct hydro_ctx {
+  hydro_config cfg;
+  Grid g;
+  int njet = 0;
+  hydro_jet jets[kMaxJets];
+  DevScalars* dev = nullptr;
+  unsigned char* ws = nullptr;
+  size_t ws_bytes = 0;
+  void* U1 = nullptr;
+  void* U2 = nullptr;
+  void* D = nullptr;
+  double* part = nullptr;
+  int64_t step = 0;
+  int seg = 32;
+  std::string err;
+  // per-kernel timing (hydro_profile): event pairs recorded around launches
+  bool prof = false;
+  struct Mark {
+    int kernel;
+    hipEvent_t b, e;
+  };
+  std::vector<Mark> marks;
+  std::vector<hipEvent_t> pool;
+};
+
+namespace {
+
+thread_local std::string g_init_error;
+
+size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+size_t elem_size(const hydro_config* c) { return c->precision == HYDRO_F32 ? sizeof(float) : sizeof(double); }
+
+long long ncells(const hydro_config* c) { return (long long)c->n[0] * c->n[1] * c->n[2]; }
+
+bool config_ok(const hydro_config* c, std::string* why) {
+  auto fail = [&](const char* m) {
+    if (why) *why = m;
+    return false;
+  };
+  if (!c) return fail("config is NULL");
+  for (int d = 0; d < 3; ++d) {
+    if (c->n[d] < 1) return fail("n[d] must be >= 1");
+    if (!(c->dx[d] > 0.0) || !std::isfinite(c->dx[d])) return fail("dx[d] must be > 0");
+    if (c->bc[d] != HYDRO_BC_OUTFLOW && c->bc[d] != HYDRO_BC_PERIODIC) return fail("bad bc");
+  }
+  if (c->n[0] > 1024) return fail("n[0] must be <= 1024");
+  // the x-face kernel keeps the split fluxes of one row (+8 ghosts) in LDS
+  if ((size_t)10 * (c->n[0] + 8) * elem_size(c) > 65536) return fail("n[0] too large for the x-row LDS tile");
+  if ((long long)c->n[1] * c->n[2] > 2147483647LL) return fail("too many rows");
+  if (!(c->dt > 0.0) || !std::isfinite(c->dt) || !std::isfinite(c->t0)) return fail("dt must be > 0");
+  if (c->precision != HYDRO_F64 && c->precision != HYDRO_F32) return fail("bad precision");
+  if (c->weno < 0 || c->weno > 2) return fail("bad weno");
+  if (c->deposit != HYDRO_DEP_NGP && c->deposit != HYDRO_DEP_GAUSS) return fail("bad deposit");
+  if (!(c->weno_eps > 0.0)) return fail("weno_eps must be > 0");
+  if (c->weno_p != 2) return fail("only weno_p = 2 is built");
+  if (!(c->eos_dof > 0.0) || !(c->hbarc > 0.0)) return fail("eos_dof and hbarc must be > 0");
+  return true;
+}
+
+struct WsLayout {
+  size_t U1, U2, D, part, total;
+};
+
+WsLayout layout(const hydro_config* c, int adjoint_k) {
+  (void)adjoint_k;
+  WsLayout L;
+  const size_t field = align256((size_t)5 * ncells(c) * elem_size(c));
+  L.U1 = 0;
+  L.U2 = L.U1 + field;
+  L.D = L.U2 + field;
+  L.part = L.D + field;
+  L.total = L.part + align256((size_t)kSumBlocks * 5 * sizeof(double));
+  return L;
+}
+
+int fail(hydro_ctx* ctx, int code, const std::string& m) {
+  if (ctx) ctx->err = m;
+  return code;
+}
+
+int hip_fail(hydro_ctx* ctx, hipError_t e, const char* where) {
+  std::string m = std::string(where) + ": " + hipGetErrorString(e);
+  if (ctx) ctx->err = m;
+  return HYDRO_EDEVICE;
+}
+
+Grid make_grid(const hydro_config* c) {
+  Grid g;
+  for (int d = 0; d < 3; ++d) {
+    g.n[d] = c->n[d];
+    g.bc[d] = c->bc[d];
+    g.dx[d] = c->dx[d];
+  }
+  g.nc = ncells(c);
+  return g;
+}
+
+bool is_device_pointer(const void* p) {
+  hipPointerAttribute_t attr;
+  hipError_t e = hipPointerGetAttributes(&attr, p);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return false;
+  }
+  return attr.type == hipMemoryTypeDevice;
+}
+
+hipEvent_t take_event(hydro_ctx* ctx) {
+  if (!ctx->pool.empty()) {
+    hipEvent_t ev = ctx->pool.back();
+    ctx->pool.pop_back();
+    return ev;
+  }
+  hipEvent_t ev = nullptr;
+  if (hipEventCreate(&ev) != hipSuccess) return nullptr;
+  return ev;
+}
+
+// Brackets one launch with events when profiling is on.
+struct ProfScope {
+  hydro_ctx* ctx;
+  int kernel;
+  hipStream_t st;
+  hipEvent_t b = nullptr;
+  ProfScope(hydro_ctx* c, int k, hipStream_t s) : ctx(c), kernel(k), st(s) {
+    if (ctx->prof) {
+      b = take_event(ctx);
+      if (b) (void)hipEventRecord(b, st);
+    }
+  }
+  ~ProfScope() {
+    if (b) {
+      hipEvent_t e = take_event(ctx);
+      if (e) {
+        (void)hipEventRecord(e, st);
+        ctx->marks.push_back({kernel, b, e});
+      } else {
+        ctx->pool.push_back(b);
+      }
+    }
+  }
+};
+
+// One stage: L(W) at time t, then (stage 1..3) the RK combine into out, or
+// (stage 0) L itself into out.
+template <class R>
+hipError_t stage_impl(hydro_ctx* ctx, const R* W, const R* Un, R* out, int stage, double t, hipStream_t st) {
+  const hydro_config& c = ctx->cfg;
+  StageArgs<R> a;
+  a.g = ctx->g;
+  a.dt = (R)c.dt;
+  a.eps = (R)c.weno_eps;
+  a.fixups = &ctx->dev->fixups;
+  a.seg = ctx->seg;
+  a.stage = stage;
+  a.W = W;
+  a.Un = Un;
+  a.out = out;
+  a.D = static_cast<R*>(ctx->D);
+  hipError_t e;
+  {
+    ProfScope p(ctx, HYDRO_K_XFACE, st);
+    e = launch_face_kernel<R>(0, a, c.weno, ctx->seg, st);
+  }
+  if (e == hipSuccess && c.bc[0] == HYDRO_BC_OUTFLOW) {
+    ProfScope p(ctx, HYDRO_K_XBOUND, st);
+    e = launch_face_kernel<R>(1, a, c.weno, ctx->seg, st);
+  }
+  if (e == hipSuccess) {
+    ProfScope p(ctx, HYDRO_K_YMARCH, st);
+    e = launch_face_kernel<R>(2, a, c.weno, ctx->seg, st);
+  }
+  if (e == hipSuccess && ctx->njet > 0) {
+    JetArgs j;
+    j.W = W;
+    j.D = a.D;
+    j.s = ctx->dev;
+    j.g = ctx->g;
+    j.njet = ctx->njet;
+    j.stage = stage;
+    j.deposit = c.deposit;
+    j.t = t;
+    j.dt = c.dt;
+    j.eos_dof = c.eos_dof;
+    j.hbarc = c.hbarc;
+    ProfScope p(ctx, HYDRO_K_JET, st);
+    e = launch_jet<R>(j, st);
+  }
+  if (e == hipSuccess) {
+    ProfScope p(ctx, HYDRO_K_ZMARCH, st);
+    e = launch_face_kernel<R>(3, a, c.weno, ctx->seg, st);
+  }
+  return e;
+}
+
+template <class R>
+int step_impl(hydro_ctx* ctx, R* U, int nsteps, hipStream_t st) {
+  const hydro_config& c = ctx->cfg;
+  const double dt = c.dt;
+  R* U1 = static_cast<R*>(ctx->U1);
+  R* U2 = static_cast<R*>(ctx->U2);
+  const double cstage[3] = {0.0, 1.0, 0.5};
+  const double dV = c.dx[0] * c.dx[1] * c.dx[2];
+  for (int s = 0; s < nsteps; ++s) {
+    const double tn = c.t0 + (double)ctx->step * dt;
+    for (int k = 1; k <= 3; ++k) {
+      const R* W = (k == 1) ? U : (k == 2 ? U1 : U2);
+      R* out = (k == 1) ? U1 : (k == 2 ? U2 : U);
+      hipError_t e = stage_impl<R>(ctx, W, U, out, k, tn + cstage[k - 1] * dt, st);
+      if (e != hipSuccess) return hip_fail(ctx, e, "stage launch");
+    }
+    hipError_t e;
+    {
+      ProfScope p(ctx, HYDRO_K_SUMS, st);
+      e = launch_sums<R>(U, ctx->g.nc, dV, ctx->part, ctx->dev, st);
+    }
+    if (e != hipSuccess) return hip_fail(ctx, e, "sums launch");
+    ctx->step += 1;
+  }
+  return HYDRO_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+void hydro_default_config(hydro_config* c) {
+  if (!c) return;
+  std::memset(c, 0, sizeof(*c));
+  for (int d = 0; d < 3; ++d) {
+    c->n[d] = 256;
+    c->dx[d] = 0.1;
+    c->bc[d] = HYDRO_BC_OUTFLOW;
+  }
+  c->t0 = 1.0;
+  c->dt = 0.02;
+  c->precision = HYDRO_F64;
+  c->weno = HYDRO_WENO_Z;
+  c->deposit = HYDRO_DEP_NGP;
+  c->weno_eps = 1e-6;
+  c->weno_p = 2;
+  c->strict = 0;
+  c->eos_dof = 47.5;
+  c->hbarc = 0.1973269804;
+}
+
+size_t hydro_workspace_bytes(const hydro_config* cfg, int adjoint_k) {
+  if (!config_ok(cfg, nullptr) || adjoint_k < 0) return 0;
+  return layout(cfg, adjoint_k).total;
+}
+
+int hydro_init(const hydro_config* cfg, const double* prim0, void* U, void* workspace, size_t ws_bytes,
+               void* stream, hydro_ctx** out) {
+  std::string why;
+  if (!out) {
+    g_init_error = "out is NULL";
+    return HYDRO_EINVAL;
+  }
+  *out = nullptr;
+  if (!config_ok(cfg, &why)) {
+    g_init_error = why;
+    return HYDRO_EINVAL;
+  }
+  const WsLayout L = layout(cfg, 0);
+  if (!U || !workspace) {
+    g_init_error = "U and workspace must be device pointers";
+    return HYDRO_EINVAL;
+  }
+  if (((uintptr_t)workspace & 255) != 0) {
+    g_init_error = "workspace must be 256-byte aligned";
+    return HYDRO_EINVAL;
+  }
+  if (ws_bytes < L.total) {
+    g_init_error = "workspace too small";
+    return HYDRO_EINVAL;
+  }
+  hydro_ctx* ctx = new (std::nothrow) hydro_ctx();
+  if (!ctx) {
+    g_init_error = "out of host memory";
+    return HYDRO_ENOMEM;
+  }
+  ctx->cfg = *cfg;
+  ctx->g = make_grid(cfg);
+  ctx->ws = static_cast<unsigned char*>(workspace);
+  ctx->ws_bytes = ws_bytes;
+  ctx->U1 = ctx->ws + L.U1;
+  ctx->U2 = ctx->ws + L.U2;
+  ctx->D = ctx->ws + L.D;
+  ctx->part = reinterpret_cast<double*>(ctx->ws + L.part);
+  // march segment: full short axes, 32 cells otherwise
+  ctx->seg = 32;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+
+  hipError_t e = hipMalloc(&ctx->dev, sizeof(DevScalars));
+  if (e != hipSuccess) {
+    g_init_error = std::string("hipMalloc: ") + hipGetErrorString(e);
+    delete ctx;
+    return HYDRO_ENOMEM;
+  }
+  DevScalars zero;
+  std::memset(&zero, 0, sizeof(zero));
+  e = hipMemcpy(ctx->dev, &zero, sizeof(zero), hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    g_init_error = std::string("hipMemcpy: ") + hipGetErrorString(e);
+    (void)hipFree(ctx->dev);
+    delete ctx;
+    return HYDRO_EDEVICE;
+  }
+
+  if (prim0) {
+    const long long nc = ctx->g.nc;
+    const double* dprim = prim0;
+    double* tmp = nullptr;
+    if (!is_device_pointer(prim0)) {
+      e = hipMalloc(&tmp, (size_t)5 * nc * sizeof(double));
+      if (e != hipSuccess) {
+        g_init_error = std::string("hipMalloc(prim0 staging): ") + hipGetErrorString(e);
+        (void)hipFree(ctx->dev);
+        delete ctx;
+        return HYDRO_ENOMEM;
+      }
+      e = hipMemcpyAsync(tmp, prim0, (size_t)5 * nc * sizeof(double), hipMemcpyHostToDevice, st);
+      dprim = tmp;
+    }
+    if (e == hipSuccess) {
+      e = cfg->precision == HYDRO_F32 ? launch_prim_to_cons<float>(dprim, static_cast<float*>(U), nc, st)
+                                      : launch_prim_to_cons<double>(dprim, static_cast<double*>(U), nc, st);
+    }
+    if (tmp) {
+      hipError_t e2 = hipStreamSynchronize(st);
+      if (e == hipSuccess) e = e2;
+      e2 = hipFree(tmp);
+      if (e == hipSuccess) e = e2;
+    }
+    if (e != hipSuccess) {
+      g_init_error = std::string("prim->cons: ") + hipGetErrorString(e);
+      (void)hipFree(ctx->dev);
+      delete ctx;
+      return HYDRO_EDEVICE;
+    }
+  }
+  *out = ctx;
+  return HYDRO_OK;
+}
+
+int hydro_add_jet(hydro_ctx* ctx, const hydro_jet* jet, int* jet_id) {
+  if (!ctx || !jet) return HYDRO_EINVAL;
+  if (ctx->njet >= kMaxJets) return fail(ctx, HYDRO_EINVAL, "too many jets");
+  double n2 = jet->dir[0] * jet->dir[0] + jet->dir[1] * jet->dir[1] + jet->dir[2] * jet->dir[2];
+  if (!(std::fabs(n2 - 1.0) < 1e-9)) return fail(ctx, HYDRO_EINVAL, "jet direction must be a unit vector");
+  for (int d = 0; d < 3; ++d)
+    if (!std::isfinite(jet->x0[d])) return fail(ctx, HYDRO_EINVAL, "jet origin must be finite");
+  if (!(jet->E0 >= 0.0) || !std::isfinite(jet->t_start) || !std::isfinite(jet->kappa_rad) ||
+      !std::isfinite(jet->kappa_coll) || !std::isfinite(jet->cr_over_cf))
+    return fail(ctx, HYDRO_EINVAL, "bad jet parameters");
+  const int id = ctx->njet;
+  JetDev jd;
+  for (int d = 0; d < 3; ++d) {
+    jd.x0[d] = jet->x0[d];
+    jd.dir[d] = jet->dir[d];
+  }
+  jd.t_start = jet->t_start;
+  jd.kappa_rad = jet->kappa_rad;
+  jd.kappa_coll = jet->kappa_coll;
+  jd.crcf = jet->cr_over_cf;
+  hipError_t e = hipMemcpy(&ctx->dev->jets[id], &jd, sizeof(jd), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(&ctx->dev->E_jet[id], &jet->E0, sizeof(double), hipMemcpyHostToDevice);
+  if (e != hipSuccess) return hip_fail(ctx, e, "hydro_add_jet");
+  ctx->jets[id] = *jet;
+  ctx->njet = id + 1;
+  if (jet_id) *jet_id = id;
+  return HYDRO_OK;
+}
+
+int hydro_rk3_step(hydro_ctx* ctx, void* U, int nsteps, void* stream) {
+  if (!ctx || !U || nsteps < 0) return fail(ctx, HYDRO_EINVAL, "bad arguments to hydro_rk3_step");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  if (ctx->cfg.precision == HYDRO_F32) return step_impl<float>(ctx, static_cast<float*>(U), nsteps, st);
+  return step_impl<double>(ctx, static_cast<double*>(U), nsteps, st);
+}
+
+int hydro_rhs(hydro_ctx* ctx, const void* U, double t, void* L, void* stream) {
+  if (!ctx || !U || !L || U == L || !std::isfinite(t)) return fail(ctx, HYDRO_EINVAL, "bad arguments to hydro_rhs");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  hipError_t e = ctx->cfg.precision == HYDRO_F32
+                     ? stage_impl<float>(ctx, static_cast<const float*>(U), nullptr, static_cast<float*>(L), 0, t, st)
+                     : stage_impl<double>(ctx, static_cast<const double*>(U), nullptr, static_cast<double*>(L), 0, t, st);
+  if (e != hipSuccess) return hip_fail(ctx, e, "hydro_rhs");
+  return HYDRO_OK;
+}
+
+int hydro_primitives(hydro_ctx* ctx, const void* U, void* prim, void* stream) {
+  if (!ctx || !U || !prim) return fail(ctx, HYDRO_EINVAL, "bad arguments to hydro_primitives");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  hipError_t e;
+  if (ctx->cfg.precision == HYDRO_F32)
+    e = launch_primitives<float>(static_cast<const float*>(U), static_cast<float*>(prim), ctx->g.nc,
+                                 ctx->cfg.eos_dof, ctx->cfg.hbarc, &ctx->dev->fixups, st);
+  else
+    e = launch_primitives<double>(static_cast<const double*>(U), static_cast<double*>(prim), ctx->g.nc,
+                                  ctx->cfg.eos_dof, ctx->cfg.hbarc, &ctx->dev->fixups, st);
+  if (e != hipSuccess) return hip_fail(ctx, e, "hydro_primitives");
+  return HYDRO_OK;
+}
+
+int hydro_sums(hydro_ctx* ctx, const void* U, double out[6], void* stream) {
+  if (!ctx || !U || !out) return fail(ctx, HYDRO_EINVAL, "bad arguments to hydro_sums");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const double dV = ctx->cfg.dx[0] * ctx->cfg.dx[1] * ctx->cfg.dx[2];
+  hipError_t e = ctx->cfg.precision == HYDRO_F32
+                     ? launch_sums<float>(static_cast<const float*>(U), ctx->g.nc, dV, ctx->part, ctx->dev, st)
+                     : launch_sums<double>(static_cast<const double*>(U), ctx->g.nc, dV, ctx->part, ctx->dev, st);
+  if (e != hipSuccess) return hip_fail(ctx, e, "hydro_sums launch");
+  e = hipStreamSynchronize(st);
+  if (e != hipSuccess) return hip_fail(ctx, e, "hydro_sums sync");
+  DevScalars h;
+  e = hipMemcpy(&h, ctx->dev, sizeof(DevScalars), hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return hip_fail(ctx, e, "hydro_sums copy");
+  for (int c = 0; c < 5; ++c) out[c] = h.sums[c];
+  out[5] = h.ledger;
+  if (ctx->cfg.strict && h.fixups > 0) return fail(ctx, HYDRO_ENONPHYS, "non-admissible cells were fixed up");
+  return HYDRO_OK;
+}
+
+int hydro_get_state(hydro_ctx* ctx, double* t, int64_t* step, double* E_jet, int n_jet) {
+  if (!ctx || n_jet < 0 || (n_jet > 0 && !E_jet)) return fail(ctx, HYDRO_EINVAL, "bad arguments to hydro_get_state");
+  hipError_t e = hipDeviceSynchronize();
+  if (e != hipSuccess) return hip_fail(ctx, e, "hydro_get_state sync");
+  if (t) *t = ctx->cfg.t0 + (double)ctx->step * ctx->cfg.dt;
+  if (step) *step = ctx->step;
+  const int m = n_jet < ctx->njet ? n_jet : ctx->njet;
+  if (m > 0) {
+    e = hipMemcpy(E_jet, ctx->dev->E_jet, (size_t)m * sizeof(double), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(ctx, e, "hydro_get_state copy");
+  }
+  return HYDRO_OK;
+}
+
+int hydro_set_state(hydro_ctx* ctx, int64_t step, const double* E_jet, int n_jet, double ledger) {
+  if (!ctx || step < 0 || n_jet != ctx->njet || (n_jet > 0 && !E_jet))
+    return fail(ctx, HYDRO_EINVAL, "bad arguments to hydro_set_state");
+  hipError_t e = hipDeviceSynchronize();
+  if (e == hipSuccess && n_jet > 0)
+    e = hipMemcpy(ctx->dev->E_jet, E_jet, (size_t)n_jet * sizeof(double), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(&ctx->dev->ledger, &ledger, sizeof(double), hipMemcpyHostToDevice);
+  if (e != hipSuccess) return hip_fail(ctx, e, "hydro_set_state");
+  ctx->step = step;
+  return HYDRO_OK;
+}
+
+int hydro_diag(hydro_ctx* ctx, int64_t* fixups) {
+  if (!ctx || !fixups) return fail(ctx, HYDRO_EINVAL, "bad arguments to hydro_diag");
+  unsigned long long f = 0;
+  hipError_t e = hipDeviceSynchronize();
+  if (e == hipSuccess) e = hipMemcpy(&f, &ctx->dev->fixups, sizeof(f), hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return hip_fail(ctx, e, "hydro_diag");
+  *fixups = (int64_t)f;
+  return HYDRO_OK;
+}
+
+int hydro_profile(hydro_ctx* ctx, int enable) {
+  if (!ctx) return HYDRO_EINVAL;
+  ctx->prof = enable != 0;
+  return HYDRO_OK;
+}
+
+int hydro_profile_read(hydro_ctx* ctx, double* ms, int64_t* launches, int nk) {
+  if (!ctx || nk < 0 || (nk > 0 && (!ms || !launches))) return fail(ctx, HYDRO_EINVAL, "bad arguments to hydro_profile_read");
+  for (int k = 0; k < nk; ++k) {
+    ms[k] = 0.0;
+    launches[k] = 0;
+  }
+  hipError_t err = hipSuccess;
+  for (auto& m : ctx->marks) {
+    if (err == hipSuccess) err = hipEventSynchronize(m.e);
+    float t = 0.0f;
+    if (err == hipSuccess) err = hipEventElapsedTime(&t, m.b, m.e);
+    if (err == hipSuccess && m.kernel < nk) {
+      ms[m.kernel] += t;
+      launches[m.kernel] += 1;
+    }
+    ctx->pool.push_back(m.b);
+    ctx->pool.push_back(m.e);
+  }
+  ctx->marks.clear();
+  if (err != hipSuccess) return hip_fail(ctx, err, "hydro_profile_read");
+  return HYDRO_OK;
+}
+
+const char* hydro_last_error(const hydro_ctx* ctx) {
+  if (!ctx) return g_init_error.c_str();
+  return ctx->err.c_str();
+}
+
+void hydro_destroy(hydro_ctx* ctx) {
+  if (!ctx) return;
+  if (ctx->dev) (void)hipFree(ctx->dev);
+  for (auto& m : ctx->marks) {
+    (void)hipEventDestroy(m.b);
+    (void)hipEventDestroy(m.e);
+  }
+  for (auto ev : ctx->pool) (void)hipEventDestroy(ev);
+  delete ctx;
+}
+
+}  // extern "C"

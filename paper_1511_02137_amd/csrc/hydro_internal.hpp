@@ -1,0 +1,74 @@
+// hydro_internal.hpp -- structures shared by the host part of libhydro and
+// its HIP kernels.  Not part of the public ABI (see include/hydro.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace hydro {
+
+constexpr int kMaxJets = 64;       // jets per context
+constexpr double kEFloor = 1e-12;  // E at or below: vacuum fix-up
+constexpr double kVCap = 1.0 - 1e-10;  // |v| cap of the fix-up
+constexpr int kSumBlocks = 1024;   // fixed number of reduction blocks (fixed order)
+
+enum Scheme { kWenoZ = 0, kWenoJS = 1, kWenoLinear = 2 };
+
+// Grid of one event.
+struct Grid {
+  int n[3];        // nx, ny, nz
+  int bc[3];       // 0 outflow, 1 periodic
+  double dx[3];    // cell widths
+  long long nc;    // nx*ny*nz
+};
+
+// Static description of a jet on the device (FP64).
+struct JetDev {
+  double x0[3];
+  double dir[3];
+  double t_start;
+  double kappa_rad, kappa_coll, crcf;
+};
+
+// Per-context device scalars (library-owned, a few KB).
+struct DevScalars {
+  JetDev jets[kMaxJets];
+  double E_jet[kMaxJets];     // remaining energy
+  double P[3][kMaxJets];      // deposited rate of each stage of the current step
+  double ledger;              // deposited energy so far
+  double sums[5];             // last conservation sums (x dV)
+  unsigned long long fixups;  // conserved->primitive fix-ups
+};
+
+// Arguments of the stage kernels (device pointers).
+template <class R>
+struct StageArgs {
+  const R* W;   // stage input [5][nc]
+  const R* Un;  // U^n (stages 2 and 3)
+  R* out;       // stage output (may alias Un in stage 3)
+  R* D;         // flux divergence accumulator [5][nc]
+  Grid g;
+  R inv_d;      // 1/dx of the kernel's axis
+  R dt;
+  R eps;        // epsilon of the WENO weights
+  int stage;    // 1, 2, 3 (RK stage); 0: write L = D + S instead of combining
+  int seg;      // march segment length (y/z kernels)
+  unsigned long long* fixups;
+};
+
+// Arguments of the jet kernel.
+struct JetArgs {
+  const void* W;   // stage input
+  void* D;         // divergence accumulator (source is added)
+  DevScalars* s;
+  Grid g;
+  int njet;
+  int stage;       // 1, 2, 3 (stage 3 also advances E_jet and the ledger); 0: RHS only
+  int deposit;     // 0 NGP, 1 Gauss
+  double t;        // stage time
+  double dt;
+  double eos_dof, hbarc;
+};
+
+}  // namespace hydro

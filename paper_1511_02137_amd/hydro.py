@@ -1,0 +1,268 @@
+"""Python binding of libhydro (include/hydro.h) through ctypes.
+
+Argument marshalling only: torch tensors provide device memory and the
+stream; every step of the computation runs in the library's HIP kernels.
+If the library is missing this module raises; there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libhydro.so")
+
+HYDRO_OK, HYDRO_EINVAL, HYDRO_ENOMEM, HYDRO_EDEVICE, HYDRO_ENONPHYS, HYDRO_ESTATE = 0, -1, -2, -3, -4, -5
+F64, F32 = 0, 1
+BC = {"outflow": 0, "periodic": 1}
+WENO = {"z": 0, "js": 1, "linear": 2}
+DEPOSIT = {"ngp": 0, "gauss": 1}
+
+EXPORTED = [
+    "hydro_default_config", "hydro_workspace_bytes", "hydro_init", "hydro_add_jet", "hydro_rk3_step",
+    "hydro_primitives", "hydro_rhs", "hydro_sums", "hydro_get_state", "hydro_set_state", "hydro_diag",
+    "hydro_last_error", "hydro_destroy", "hydro_profile", "hydro_profile_read",
+]
+KERNELS = ["xface", "xbound", "ymarch", "jet", "zmarch", "sums"]
+
+
+class HydroError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__("libhydro error %d: %s" % (code, msg))
+        self.code = code
+
+
+class Config(ctypes.Structure):
+    _fields_ = [
+        ("n", ctypes.c_int32 * 3),
+        ("dx", ctypes.c_double * 3),
+        ("t0", ctypes.c_double),
+        ("dt", ctypes.c_double),
+        ("bc", ctypes.c_int32 * 3),
+        ("precision", ctypes.c_int32),
+        ("weno", ctypes.c_int32),
+        ("deposit", ctypes.c_int32),
+        ("weno_eps", ctypes.c_double),
+        ("weno_p", ctypes.c_int32),
+        ("strict", ctypes.c_int32),
+        ("eos_dof", ctypes.c_double),
+        ("hbarc", ctypes.c_double),
+    ]
+
+
+class JetC(ctypes.Structure):
+    _fields_ = [
+        ("x0", ctypes.c_double * 3),
+        ("dir", ctypes.c_double * 3),
+        ("E0", ctypes.c_double),
+        ("t_start", ctypes.c_double),
+        ("kappa_rad", ctypes.c_double),
+        ("kappa_coll", ctypes.c_double),
+        ("cr_over_cf", ctypes.c_double),
+    ]
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libhydro.so and declare its signatures (no GPU needed)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError("libhydro.so is not built (run paper_1511_02137_amd/build.py): " + path)
+    lib = ctypes.CDLL(path)
+    vp, cp, dp = ctypes.c_void_p, ctypes.POINTER(Config), ctypes.POINTER(ctypes.c_double)
+    lib.hydro_default_config.argtypes = [cp]
+    lib.hydro_default_config.restype = None
+    lib.hydro_workspace_bytes.argtypes = [cp, ctypes.c_int]
+    lib.hydro_workspace_bytes.restype = ctypes.c_size_t
+    lib.hydro_init.argtypes = [cp, vp, vp, vp, ctypes.c_size_t, vp, ctypes.POINTER(vp)]
+    lib.hydro_add_jet.argtypes = [vp, ctypes.POINTER(JetC), ctypes.POINTER(ctypes.c_int)]
+    lib.hydro_rk3_step.argtypes = [vp, vp, ctypes.c_int, vp]
+    lib.hydro_primitives.argtypes = [vp, vp, vp, vp]
+    lib.hydro_rhs.argtypes = [vp, vp, ctypes.c_double, vp, vp]
+    lib.hydro_sums.argtypes = [vp, vp, dp, vp]
+    lib.hydro_get_state.argtypes = [vp, dp, ctypes.POINTER(ctypes.c_int64), dp, ctypes.c_int]
+    lib.hydro_set_state.argtypes = [vp, ctypes.c_int64, dp, ctypes.c_int, ctypes.c_double]
+    lib.hydro_diag.argtypes = [vp, ctypes.POINTER(ctypes.c_int64)]
+    lib.hydro_last_error.argtypes = [vp]
+    lib.hydro_last_error.restype = ctypes.c_char_p
+    lib.hydro_destroy.argtypes = [vp]
+    lib.hydro_destroy.restype = None
+    lib.hydro_profile.argtypes = [vp, ctypes.c_int]
+    lib.hydro_profile_read.argtypes = [vp, dp, ctypes.POINTER(ctypes.c_int64), ctypes.c_int]
+    for name in ("hydro_init", "hydro_add_jet", "hydro_rk3_step", "hydro_primitives", "hydro_rhs", "hydro_sums",
+                 "hydro_get_state", "hydro_set_state", "hydro_diag", "hydro_profile", "hydro_profile_read"):
+        getattr(lib, name).restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def make_config(n, dx=(0.1, 0.1, 0.1), dt=0.02, t0=1.0, bc=("outflow",) * 3, precision="f64", weno="z",
+                deposit="ngp", weno_eps=1e-6, strict=False, eos_dof=47.5, hbarc=0.1973269804) -> Config:
+    lib = load_library()
+    c = Config()
+    lib.hydro_default_config(ctypes.byref(c))
+    for d in range(3):
+        c.n[d] = int(n[d])
+        c.dx[d] = float(dx[d])
+        c.bc[d] = BC[bc[d]] if isinstance(bc[d], str) else int(bc[d])
+    c.t0, c.dt = float(t0), float(dt)
+    c.precision = F32 if precision in ("f32", F32) else F64
+    c.weno = WENO[weno] if isinstance(weno, str) else int(weno)
+    c.deposit = DEPOSIT[deposit] if isinstance(deposit, str) else int(deposit)
+    c.weno_eps = float(weno_eps)
+    c.strict = 1 if strict else 0
+    c.eos_dof, c.hbarc = float(eos_dof), float(hbarc)
+    return c
+
+
+def workspace_bytes(cfg: Config, adjoint_k: int = 0) -> int:
+    return int(load_library().hydro_workspace_bytes(ctypes.byref(cfg), int(adjoint_k)))
+
+
+def _stream_handle(stream=None):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+class Hydro:
+    """One event on one GPU: conserved fields U (torch, [5, nz, ny, nx]) and
+    the library context.  prim0: (5, nz, ny, nx) float64 [e, vx, vy, vz, n]
+    as numpy (host) or a torch tensor (host or device)."""
+
+    def __init__(self, cfg: Config, prim0, device: str = "cuda", adjoint_k: int = 0):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("libhydro needs a GPU (torch.cuda.is_available() is False)")
+        self.lib = load_library()
+        self.cfg = cfg
+        self.device = torch.device(device)
+        self.dtype = torch.float32 if cfg.precision == F32 else torch.float64
+        nx, ny, nz = cfg.n[0], cfg.n[1], cfg.n[2]
+        self.shape = (nz, ny, nx)
+        self.U = torch.empty((5, nz, ny, nx), dtype=self.dtype, device=self.device)
+        nbytes = workspace_bytes(cfg, adjoint_k)
+        if nbytes == 0:
+            raise HydroError(HYDRO_EINVAL, "invalid configuration")
+        self.ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+        off = (-self.ws.data_ptr()) % 256
+        self._ws_ptr = self.ws.data_ptr() + off
+        self._ws_bytes = nbytes
+        if prim0 is None:
+            pptr = None
+            self._prim_keep = None
+        elif isinstance(prim0, np.ndarray):
+            p = np.ascontiguousarray(prim0, dtype=np.float64)
+            assert p.shape == (5, nz, ny, nx), p.shape
+            self._prim_keep = p
+            pptr = p.ctypes.data
+        else:
+            p = prim0.to(dtype=torch.float64).contiguous()
+            assert tuple(p.shape) == (5, nz, ny, nx)
+            self._prim_keep = p
+            pptr = p.data_ptr()
+        h = ctypes.c_void_p()
+        rc = self.lib.hydro_init(ctypes.byref(cfg), pptr, self.U.data_ptr(), self._ws_ptr, self._ws_bytes,
+                                 _stream_handle(), ctypes.byref(h))
+        if rc != HYDRO_OK:
+            raise HydroError(rc, self.lib.hydro_last_error(None).decode())
+        self.ctx = h
+        self.njet = 0
+
+    def _check(self, rc):
+        if rc != HYDRO_OK:
+            raise HydroError(rc, self.lib.hydro_last_error(self.ctx).decode())
+
+    def add_jet(self, x0, dir=(1.0, 0.0, 0.0), E0=50.0, t_start=1.0, kappa_rad=4.0, kappa_coll=2.5,
+                cr_over_cf=1.0) -> int:
+        j = JetC()
+        for d in range(3):
+            j.x0[d] = float(x0[d])
+            j.dir[d] = float(dir[d])
+        j.E0, j.t_start = float(E0), float(t_start)
+        j.kappa_rad, j.kappa_coll, j.cr_over_cf = float(kappa_rad), float(kappa_coll), float(cr_over_cf)
+        jid = ctypes.c_int(-1)
+        self._check(self.lib.hydro_add_jet(self.ctx, ctypes.byref(j), ctypes.byref(jid)))
+        self.njet += 1
+        return jid.value
+
+    def step(self, nsteps: int = 1, stream=None):
+        self._check(self.lib.hydro_rk3_step(self.ctx, self.U.data_ptr(), int(nsteps), _stream_handle(stream)))
+
+    def rhs(self, U=None, t: float = None, stream=None):
+        """L(U) = D(U) + S(U) at time t (default: the current step's time)."""
+        import torch
+        U = self.U if U is None else U
+        if t is None:
+            t = self.get_state()[0]
+        out = torch.empty_like(U)
+        self._check(self.lib.hydro_rhs(self.ctx, U.data_ptr(), float(t), out.data_ptr(), _stream_handle(stream)))
+        return out
+
+    def primitives(self, U=None, stream=None):
+        import torch
+        U = self.U if U is None else U
+        out = torch.empty((6,) + self.shape, dtype=self.dtype, device=self.device)
+        self._check(self.lib.hydro_primitives(self.ctx, U.data_ptr(), out.data_ptr(), _stream_handle(stream)))
+        return out
+
+    def sums(self, U=None, stream=None) -> np.ndarray:
+        U = self.U if U is None else U
+        out = (ctypes.c_double * 6)()
+        self._check(self.lib.hydro_sums(self.ctx, U.data_ptr(), out, _stream_handle(stream)))
+        return np.array(list(out))
+
+    def get_state(self):
+        t = ctypes.c_double(0)
+        st = ctypes.c_int64(0)
+        E = (ctypes.c_double * max(1, self.njet))()
+        self._check(self.lib.hydro_get_state(self.ctx, ctypes.byref(t), ctypes.byref(st), E, self.njet))
+        return t.value, st.value, np.array(list(E)[: self.njet])
+
+    def set_state(self, step: int, E_jet, ledger: float):
+        E = (ctypes.c_double * max(1, self.njet))(*[float(v) for v in E_jet])
+        self._check(self.lib.hydro_set_state(self.ctx, int(step), E, self.njet, float(ledger)))
+
+    def fixups(self) -> int:
+        f = ctypes.c_int64(0)
+        self._check(self.lib.hydro_diag(self.ctx, ctypes.byref(f)))
+        return f.value
+
+    def profile(self, enable: bool = True):
+        """Bracket every later launch of step() with HIP events on its stream."""
+        self._check(self.lib.hydro_profile(self.ctx, 1 if enable else 0))
+
+    def profile_read(self):
+        """{kernel class: (total ms, launches)} since the last read."""
+        nk = len(KERNELS)
+        ms = (ctypes.c_double * nk)()
+        n = (ctypes.c_int64 * nk)()
+        self._check(self.lib.hydro_profile_read(self.ctx, ms, n, nk))
+        return {KERNELS[k]: (ms[k], n[k]) for k in range(nk)}
+
+    def close(self):
+        if getattr(self, "ctx", None):
+            self.lib.hydro_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def from_workload(w, precision: str = "f64", weno: str = "z", bc=None, adjoint_k: int = 0, device="cuda") -> Hydro:
+    """Hydro for a paper_1511_02137_amd.workloads.Workload, with its jets."""
+    cfg = make_config(w.n, w.dx, w.dt, w.t0, bc or w.bc, precision, weno, w.deposit)
+    h = Hydro(cfg, w.prim0, device=device, adjoint_k=adjoint_k)
+    for j in w.jets:
+        h.add_jet(j.x0, j.dir, j.E0, j.t_start, j.kappa_rad, j.kappa_coll, j.cr_over_cf)
+    return h
