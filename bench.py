@@ -87,6 +87,9 @@ def main():
     ap.add_argument("--n", type=int, default=256, help="cells per axis")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target length of the CPU oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--yz", choices=["tile", "march"], default="tile", help="y/z face kernels")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only run a plain device copy of 1 GiB 10 times (scale for the HBM counters)")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -98,8 +101,19 @@ def main():
     from paper_1511_02137_amd import hydro as H
     from paper_1511_02137_amd import workloads as W
 
+    if args.calibrate_copy:
+        a = torch.ones(1 << 27, dtype=torch.float64, device="cuda")  # 1 GiB
+        b = torch.empty_like(a)
+        for _ in range(10):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"calibrate_copy_bytes_read": a.numel() * 8, "calibrate_copy_bytes_written": b.numel() * 8,
+                          "launches": 10}))
+        return
+
     w = W.paper_event(2, n=(args.n,) * 3)
     h = H.from_workload(w, precision=args.precision)
+    h.set_option(H.OPT_YZ_KERNEL, 0 if args.yz == "tile" else 1)
     nc = w.n[0] * w.n[1] * w.n[2]
 
     h.step(args.warmup)
@@ -144,7 +158,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": "%s: %d^3 cells, dx 0.1 fm, dt 0.02 fm/c, p = e/3, WENO7-Z + LF split, "
                                "SSP-RK3, 1 jet (NGP), outflow" % (w.name, args.n),
-                   "grid": list(w.n), "precision": args.precision, "jets": len(w.jets)},
+                   "grid": list(w.n), "precision": args.precision, "jets": len(w.jets), "yz_kernel": args.yz},
         "roofline": roofline,
         "step_alu_frac": step_frac,
         "flops_per_cell_update": FLOPS_PER_CELL_UPDATE,

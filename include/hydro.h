@@ -68,7 +68,8 @@ typedef enum {
 typedef enum { HYDRO_WENO_Z = 0, HYDRO_WENO_JS = 1, HYDRO_WENO_LINEAR = 2 } hydro_weno;
 
 typedef struct {
-  int32_t n[3];        /* cells along x, y, z >= 1; n[0] <= 810 (FP64) or 1024 (FP32) */
+  int32_t n[3];        /* cells along x, y, z >= 1; n[0] <= 810 (FP64) or 1024 (FP32),
+                          n[1], n[2] <= 65535 */
   double dx[3];        /* cell widths [fm], > 0 */
   double t0;           /* initial time [fm/c] */
   double dt;           /* time step [fm/c], > 0 */
@@ -159,13 +160,24 @@ int hydro_set_state(hydro_ctx* ctx, int64_t step, const double* E_jet, int n_jet
 /* Synchronous: number of conserved->primitive fix-ups so far. */
 int hydro_diag(hydro_ctx* ctx, int64_t* fixups);
 
+/* Launch-shape options of a context (results do not depend on them: every
+ * variant computes each face with the same arithmetic). */
+typedef enum {
+  HYDRO_OPT_YZ_KERNEL = 0,  /* y/z faces: 0 = LDS tiles (default), 1 = register marches */
+  HYDRO_OPT_MARCH_SEG = 1   /* cells per march segment (default 32) */
+} hydro_option;
+
+/* Set / read an option; HYDRO_EINVAL for an unknown option or bad value. */
+int hydro_set_option(hydro_ctx* ctx, int option, int value);
+int hydro_get_option(hydro_ctx* ctx, int option, int* value);
+
 /* Kernel classes of a step, for hydro_profile_read. */
 typedef enum {
   HYDRO_K_XFACE = 0,   /* x-faces of every row */
   HYDRO_K_XBOUND = 1,  /* right boundary x-face of every row (outflow) */
-  HYDRO_K_YMARCH = 2,  /* y-faces (march along y) */
+  HYDRO_K_YMARCH = 2,  /* y-faces (LDS tiles or marches along y) */
   HYDRO_K_JET = 3,     /* jet source */
-  HYDRO_K_ZMARCH = 4,  /* z-faces (march along z) and the RK combine */
+  HYDRO_K_ZMARCH = 4,  /* z-faces (LDS tiles or marches along z) and the RK combine */
   HYDRO_K_SUMS = 5,    /* FP64 conservation sums */
   HYDRO_NK = 6
 } hydro_kernel_class;

@@ -46,7 +46,8 @@ struct hydro_ctx {
   void* D = nullptr;
   double* part = nullptr;
   int64_t step = 0;
-  int seg = 32;
+  int seg = 32;      // march segment length
+  int yz_tile = 1;   // 1: y/z faces from LDS tiles, 0: register-window marches
   std::string err;
   // per-kernel timing (hydro_profile): event pairs recorded around launches
   bool prof = false;
@@ -83,6 +84,7 @@ bool config_ok(const hydro_config* c, std::string* why) {
   // the x-face kernel keeps the split fluxes of one row (+8 ghosts) in LDS
   if ((size_t)10 * (c->n[0] + 8) * elem_size(c) > 65536) return fail("n[0] too large for the x-row LDS tile");
   if ((long long)c->n[1] * c->n[2] > 2147483647LL) return fail("too many rows");
+  if (c->n[1] > 65535 || c->n[2] > 65535) return fail("n[1], n[2] must be <= 65535");
   if (!(c->dt > 0.0) || !std::isfinite(c->dt) || !std::isfinite(c->t0)) return fail("dt must be > 0");
   if (c->precision != HYDRO_F64 && c->precision != HYDRO_F32) return fail("bad precision");
   if (c->weno < 0 || c->weno > 2) return fail("bad weno");
@@ -204,7 +206,7 @@ hipError_t stage_impl(hydro_ctx* ctx, const R* W, const R* Un, R* out, int stage
   }
   if (e == hipSuccess) {
     ProfScope p(ctx, HYDRO_K_YMARCH, st);
-    e = launch_face_kernel<R>(2, a, c.weno, ctx->seg, st);
+    e = launch_face_kernel<R>(ctx->yz_tile ? 4 : 2, a, c.weno, ctx->seg, st);
   }
   if (e == hipSuccess && ctx->njet > 0) {
     JetArgs j;
@@ -224,7 +226,7 @@ hipError_t stage_impl(hydro_ctx* ctx, const R* W, const R* Un, R* out, int stage
   }
   if (e == hipSuccess) {
     ProfScope p(ctx, HYDRO_K_ZMARCH, st);
-    e = launch_face_kernel<R>(3, a, c.weno, ctx->seg, st);
+    e = launch_face_kernel<R>(ctx->yz_tile ? 5 : 3, a, c.weno, ctx->seg, st);
   }
   return e;
 }
@@ -492,6 +494,31 @@ int hydro_diag(hydro_ctx* ctx, int64_t* fixups) {
   if (e != hipSuccess) return hip_fail(ctx, e, "hydro_diag");
   *fixups = (int64_t)f;
   return HYDRO_OK;
+}
+
+int hydro_set_option(hydro_ctx* ctx, int option, int value) {
+  if (!ctx) return HYDRO_EINVAL;
+  switch (option) {
+    case HYDRO_OPT_YZ_KERNEL:
+      if (value != 0 && value != 1) return fail(ctx, HYDRO_EINVAL, "HYDRO_OPT_YZ_KERNEL takes 0 or 1");
+      ctx->yz_tile = value == 0 ? 1 : 0;
+      return HYDRO_OK;
+    case HYDRO_OPT_MARCH_SEG:
+      if (value < 1 || value > 4096) return fail(ctx, HYDRO_EINVAL, "HYDRO_OPT_MARCH_SEG must be in [1, 4096]");
+      ctx->seg = value;
+      return HYDRO_OK;
+    default:
+      return fail(ctx, HYDRO_EINVAL, "unknown option");
+  }
+}
+
+int hydro_get_option(hydro_ctx* ctx, int option, int* value) {
+  if (!ctx || !value) return HYDRO_EINVAL;
+  switch (option) {
+    case HYDRO_OPT_YZ_KERNEL: *value = ctx->yz_tile ? 0 : 1; return HYDRO_OK;
+    case HYDRO_OPT_MARCH_SEG: *value = ctx->seg; return HYDRO_OK;
+    default: return fail(ctx, HYDRO_EINVAL, "unknown option");
+  }
 }
 
 int hydro_profile(hydro_ctx* ctx, int enable) {

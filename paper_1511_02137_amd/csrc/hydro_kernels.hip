@@ -106,8 +106,9 @@ __device__ __forceinline__ void split_flux(const R u[5], const PrimV& p, R Fp[5]
 
 // ---------------------------------------------------------------------------
 // WENO7 value at x_{i+1/2} from the left, a0..a6 = a_{i-3}..a_{i+3}.
-// Candidates q_k on the 4-point stencils enter pre-multiplied by the ideal
-// weights d = (1, 12, 18, 4)/35.  Smoothness indicators (Jiang-Shu: the
+// The candidates q_k of the 4-point stencils enter as d_k (q_k - a_{i}),
+// d = (1, 12, 18, 4)/35, written with the first differences, and the result
+// is a_i + sum w_k d_k (q_k - a_i) / sum w_k d_k.  Smoothness indicators (Jiang-Shu: the
 // integral over cell i of the squared derivatives of stencil k's cubic) are
 // evaluated from the nested differences D1, D2, D3 of the stencil values:
 //   b_k = s_k^2 + 13/12 c_k^2 + 781/720 D3_k^2 + eps,
@@ -135,15 +136,33 @@ __device__ __forceinline__ R smoothness(R D1, R D2, R D3, R h, R m, R g, R eps) 
   return fma(sk, sk, fma(R(13.0 / 12.0) * ck, ck, fma(R(781.0 / 720.0) * D3, D3, eps)));
 }
 
+// Reciprocal for FP64: hardware estimate, two Newton steps (quadratic
+// convergence from the estimate's ~23 bits to full precision).
+__device__ __forceinline__ double rcp_nr(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  r = fma(fma(-x, r, 1.0), r, r);
+  r = fma(fma(-x, r, 1.0), r, r);
+  return r;
+}
+
+// num / den from one reciprocal plus a residual correction.
+__device__ __forceinline__ double div_nr(double num, double den) {
+  const double r = rcp_nr(den);
+  const double q = num * r;
+  return fma(fma(-den, q, num), r, q);
+}
+
 template <class R, int S>
 __device__ __forceinline__ R weno7(R a0, R a1, R a2, R a3, R a4, R a5, R a6, R eps) {
-  const R dq0 = fma(R(25.0 / 420.0), a3, fma(R(-23.0 / 420.0), a2, fma(R(13.0 / 420.0), a1, R(-3.0 / 420.0) * a0)));
-  const R dq1 = fma(R(3.0 / 35.0), a4, fma(R(13.0 / 35.0), a3, fma(R(-5.0 / 35.0), a2, R(1.0 / 35.0) * a1)));
-  const R dq2 = fma(R(-3.0 / 70.0), a5, fma(R(21.0 / 70.0), a4, fma(R(21.0 / 70.0), a3, R(-3.0 / 70.0) * a2)));
-  const R dq3 = fma(R(1.0 / 105.0), a6, fma(R(-5.0 / 105.0), a5, fma(R(13.0 / 105.0), a4, R(3.0 / 105.0) * a3)));
-  if (S == kWenoLinear) return (dq0 + dq1) + (dq2 + dq3);
-
+  // nested differences of the seven values
   const R e0 = a1 - a0, e1 = a2 - a1, e2 = a3 - a2, e3 = a4 - a3, e4 = a5 - a4, e5 = a6 - a5;
+  // candidates as d_k (q_k - a3), from the differences
+  const R r0 = fma(R(13.0 / 420.0), e2, fma(R(-10.0 / 420.0), e1, R(3.0 / 420.0) * e0));
+  const R r1 = fma(R(3.0 / 35.0), e3, fma(R(4.0 / 35.0), e2, R(-1.0 / 35.0) * e1));
+  const R r2 = fma(R(-3.0 / 70.0), e4, fma(R(18.0 / 70.0), e3, R(3.0 / 70.0) * e2));
+  const R r3 = fma(R(1.0 / 105.0), e5, fma(R(-4.0 / 105.0), e4, R(9.0 / 105.0) * e3));
+  if (S == kWenoLinear) return a3 + ((r0 + r1) + (r2 + r3));
+
   const R f0 = e1 - e0, f1 = e2 - e1, f2 = e3 - e2, f3 = e4 - e3, f4 = e5 - e4;
   const R g0 = f1 - f0, g1 = f2 - f1, g2 = f3 - f2, g3 = f4 - f3;
   const R b0 = smoothness<R>(e0, f0, g0, R(2.5), R(11.0 / 6.0), R(2), eps);
@@ -151,42 +170,44 @@ __device__ __forceinline__ R weno7(R a0, R a1, R a2, R a3, R a4, R a5, R a6, R e
   const R b2 = smoothness<R>(e2, f2, g2, R(0.5), R(-1.0 / 6.0), R(0), eps);
   const R b3 = smoothness<R>(e3, f3, g3, R(-0.5), R(1.0 / 3.0), R(-1), eps);
 
-  R i0, i1, i2, i3;
   if (sizeof(R) == 8) {
-    // one division for the four reciprocals
-    const R p01 = b0 * b1;
-    const R p23 = b2 * b3;
-    const R inv = R(1) / (p01 * p23);
-    const R u23 = inv * p23;
-    const R u01 = inv * p01;
-    i0 = u23 * b1;
-    i1 = u23 * b0;
-    i2 = u01 * b3;
-    i3 = u01 * b2;
+    // Weights over a common denominator: with B_k = b_k^2 the WENO-Z weight
+    // d_k (1 + tau^2/B_k) is proportional to d_k (B_k + tau^2) prod_{j!=k} B_j,
+    // the Jiang-Shu weight d_k/B_k to d_k prod_{j!=k} B_j.  One division.
+    const R B0 = b0 * b0, B1 = b1 * b1, B2 = b2 * b2, B3 = b3 * b3;
+    const R P01 = B0 * B1, P23 = B2 * B3;
+    R A0 = B1 * P23, A1 = B0 * P23, A2 = P01 * B3, A3 = P01 * B2;
+    if (S == kWenoZ) {
+      const R tau = fabs(fma(R(3), b1 - b2, b0 - b3));
+      const R t2 = tau * tau;
+      A0 = (B0 + t2) * A0;
+      A1 = (B1 + t2) * A1;
+      A2 = (B2 + t2) * A2;
+      A3 = (B3 + t2) * A3;
+    }
+    const R num = fma(A3, r3, fma(A2, r2, fma(A1, r1, A0 * r0)));
+    const R den = fma(A3, R(4.0 / 35.0), fma(A2, R(18.0 / 35.0), fma(A1, R(12.0 / 35.0), A0 * R(1.0 / 35.0))));
+    return a3 + (R)div_nr((double)num, (double)den);
   } else {
-    i0 = rcp_approx<R>(b0);
-    i1 = rcp_approx<R>(b1);
-    i2 = rcp_approx<R>(b2);
-    i3 = rcp_approx<R>(b3);
+    const R i0 = rcp_approx<R>(b0), i1 = rcp_approx<R>(b1), i2 = rcp_approx<R>(b2), i3 = rcp_approx<R>(b3);
+    R w0, w1, w2, w3;
+    if (S == kWenoZ) {
+      const R tau = fabs(fma(R(3), b1 - b2, b0 - b3));
+      const R s0 = tau * i0, s1 = tau * i1, s2 = tau * i2, s3 = tau * i3;
+      w0 = fma(s0, s0, R(1));
+      w1 = fma(s1, s1, R(1));
+      w2 = fma(s2, s2, R(1));
+      w3 = fma(s3, s3, R(1));
+    } else {
+      w0 = i0 * i0;
+      w1 = i1 * i1;
+      w2 = i2 * i2;
+      w3 = i3 * i3;
+    }
+    const R num = fma(w3, r3, fma(w2, r2, fma(w1, r1, w0 * r0)));
+    const R den = fma(w3, R(4.0 / 35.0), fma(w2, R(18.0 / 35.0), fma(w1, R(12.0 / 35.0), w0 * R(1.0 / 35.0))));
+    return fma(num, rcp_approx<R>(den), a3);
   }
-  R w0, w1, w2, w3;
-  if (S == kWenoZ) {
-    const R tau = fabs(fma(R(3), b1 - b2, b0 - b3));
-    const R s0 = tau * i0, s1 = tau * i1, s2 = tau * i2, s3 = tau * i3;
-    w0 = fma(s0, s0, R(1));
-    w1 = fma(s1, s1, R(1));
-    w2 = fma(s2, s2, R(1));
-    w3 = fma(s3, s3, R(1));
-  } else {
-    w0 = i0 * i0;
-    w1 = i1 * i1;
-    w2 = i2 * i2;
-    w3 = i3 * i3;
-  }
-  const R num = fma(w3, dq3, fma(w2, dq2, fma(w1, dq1, w0 * dq0)));
-  const R den = fma(w3, R(4.0 / 35.0), fma(w2, R(18.0 / 35.0), fma(w1, R(12.0 / 35.0), w0 * R(1.0 / 35.0))));
-  if (sizeof(R) == 8) return num / den;
-  return num * rcp_approx<R>(den);
 }
 
 // Face flux from the 8-point window Fp/Fm[m] = split fluxes at i-3+m:
@@ -372,6 +393,143 @@ __global__ void __launch_bounds__(256) k_march(StageArgs<R> a) {
         R outv;
         if (a.stage == 0) {
           outv = L;  // right-hand side only
+        } else if (a.stage == 1) {
+          outv = w + a.dt * L;
+        } else if (a.stage == 2) {
+          outv = R(0.75) * a.Un[c * nc + cell] + R(0.25) * (w + a.dt * L);
+        } else {
+          outv = R(1.0 / 3.0) * a.Un[c * nc + cell] + R(2.0 / 3.0) * (w + a.dt * L);
+        }
+        a.out[c * nc + cell] = outv;
+      }
+    }
+  }
+  add_fixups(a.fixups, fix);
+}
+
+// ---------------------------------------------------------------------------
+// y- or z-faces from an LDS tile (AX = 1 or 2).  A workgroup of 512 lanes
+// owns 16 cells along x (coalesced 128-byte rows) by 32 cells along AX at one
+// value of the remaining axis.  It stores the split AX-fluxes of its 16 x 40
+// points (4 ghost rows on each side) in LDS, reconstructs the 33 face rows
+// (one face per lane, one extra row for 16 lanes) and forms the divergence.
+// LAST (z): adds D, does the RK combine with the cell's own stage input kept
+// in registers from the load, and writes the stage output.
+constexpr int kTileX = 16;
+constexpr int kTileA = 32;
+constexpr int kTileP = kTileA + 8;   // points along AX
+constexpr int kTileXP = kTileX;      // x pitch of the LDS arrays (128-byte rows)
+
+template <class R, int S, int AX, bool LAST>
+__global__ void __launch_bounds__(512) k_tile(StageArgs<R> a) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  R* s = reinterpret_cast<R*>(smem_raw);
+  R* sFp = s;                              // [5][kTileP][kTileXP]
+  R* sFm = s + 5 * kTileP * kTileXP;       // [5][kTileP][kTileXP]
+  const int nx = a.g.n[0], ny = a.g.n[1];
+  const int n = a.g.n[AX];
+  const int bc = a.g.bc[AX];
+  const long long nc = a.g.nc;
+  const int tx = threadIdx.x & (kTileX - 1);
+  const int ta = threadIdx.x >> 4;  // 0..31
+  const int x = blockIdx.x * kTileX + tx;
+  const int a0 = blockIdx.y * kTileA;
+  const int o = blockIdx.z;
+  const long long stride = (AX == 1) ? (long long)nx : (long long)nx * ny;
+  const long long base = (AX == 1) ? (long long)o * nx * ny + x : (long long)o * nx + x;
+  const bool xin = x < nx;
+  unsigned fix = 0;
+
+  R own[5];
+  // pass 1: own cell (slot ta + 4)
+  {
+    const int p = a0 + ta;
+    if (xin) {
+      load5(a.W, nc, base + (long long)map_idx(p, n, bc) * stride, own);
+      const PrimV pv = c2p(own, fix);
+      R Fp[5], Fm[5];
+      split_flux<R, AX>(own, pv, Fp, Fm);
+#pragma unroll
+      for (int c = 0; c < 5; ++c) {
+        sFp[(c * kTileP + ta + 4) * kTileXP + tx] = Fp[c];
+        sFm[(c * kTileP + ta + 4) * kTileXP + tx] = Fm[c];
+      }
+    }
+  }
+  // pass 2: 4 ghost rows on each side (128 lanes)
+  if (threadIdx.x < 8 * kTileX) {
+    const int h = ta;  // 0..7
+    const int j = (h < 4) ? h : h + kTileA;
+    const int p = a0 - 4 + j;
+    if (xin) {
+      R u[5];
+      load5(a.W, nc, base + (long long)map_idx(p, n, bc) * stride, u);
+      const PrimV pv = c2p(u, fix);
+      R Fp[5], Fm[5];
+      split_flux<R, AX>(u, pv, Fp, Fm);
+#pragma unroll
+      for (int c = 0; c < 5; ++c) {
+        sFp[(c * kTileP + j) * kTileXP + tx] = Fp[c];
+        sFm[(c * kTileP + j) * kTileXP + tx] = Fm[c];
+      }
+    }
+  }
+  __syncthreads();
+
+  // faces f = 0..32: face (a0 - 1 + f) + 1/2; F+ at slots f..f+6, F- at f+1..f+7
+  const int nf = min(kTileA, n - a0) + 1;  // face rows this tile needs
+  R Fh[5], Fh2[5];
+  const bool has1 = xin && ta < nf;
+  const bool has2 = xin && threadIdx.x < kTileX && kTileA < nf;
+  if (has1) {
+#pragma unroll
+    for (int c = 0; c < 5; ++c) {
+      const R* fp = sFp + (c * kTileP + ta) * kTileXP + tx;
+      const R* fm = sFm + (c * kTileP + ta) * kTileXP + tx;
+      Fh[c] = weno7<R, S>(fp[0], fp[kTileXP], fp[2 * kTileXP], fp[3 * kTileXP], fp[4 * kTileXP], fp[5 * kTileXP],
+                          fp[6 * kTileXP], a.eps) +
+              weno7<R, S>(fm[7 * kTileXP], fm[6 * kTileXP], fm[5 * kTileXP], fm[4 * kTileXP], fm[3 * kTileXP],
+                          fm[2 * kTileXP], fm[kTileXP], a.eps);
+    }
+  }
+  if (has2) {
+#pragma unroll
+    for (int c = 0; c < 5; ++c) {
+      const R* fp = sFp + (c * kTileP + kTileA) * kTileXP + tx;
+      const R* fm = sFm + (c * kTileP + kTileA) * kTileXP + tx;
+      Fh2[c] = weno7<R, S>(fp[0], fp[kTileXP], fp[2 * kTileXP], fp[3 * kTileXP], fp[4 * kTileXP], fp[5 * kTileXP],
+                           fp[6 * kTileXP], a.eps) +
+               weno7<R, S>(fm[7 * kTileXP], fm[6 * kTileXP], fm[5 * kTileXP], fm[4 * kTileXP], fm[3 * kTileXP],
+                           fm[2 * kTileXP], fm[kTileXP], a.eps);
+    }
+  }
+  __syncthreads();
+  R* sF = s;  // [5][kTileA + 1][kTileXP]
+  if (has1) {
+#pragma unroll
+    for (int c = 0; c < 5; ++c) sF[(c * (kTileA + 1) + ta) * kTileXP + tx] = Fh[c];
+  }
+  if (has2) {
+#pragma unroll
+    for (int c = 0; c < 5; ++c) sF[(c * (kTileA + 1) + kTileA) * kTileXP + tx] = Fh2[c];
+  }
+  __syncthreads();
+
+  const int ac = a0 + ta;
+  if (xin && ac < n) {
+    const long long cell = base + (long long)ac * stride;
+#pragma unroll
+    for (int c = 0; c < 5; ++c) {
+      const R div = (sF[(c * (kTileA + 1) + ta) * kTileXP + tx] - sF[(c * (kTileA + 1) + ta + 1) * kTileXP + tx]) * a.inv_d;
+      R* d = a.D + c * nc + cell;
+      if (!LAST) {
+        *d = *d + div;
+      } else {
+        const R L = *d + div;
+        const R w = own[c];
+        R outv;
+        if (a.stage == 0) {
+          outv = L;
         } else if (a.stage == 1) {
           outv = w + a.dt * L;
         } else if (a.stage == 2) {
@@ -630,7 +788,20 @@ void launch_march_t(const StageArgs<R>& base, int seg, hipStream_t st) {
   hipLaunchKernelGGL((k_march<R, S, AX, AX == 2>), grid, dim3(64, 4), 0, st, a);
 }
 
-// kernel: 0 x-faces, 1 x boundary faces, 2 y-march, 4 z-march (+ combine)
+template <class R, int S, int AX>
+void launch_tile_t(const StageArgs<R>& base, hipStream_t st) {
+  StageArgs<R> a = base;
+  const int nx = a.g.n[0];
+  a.inv_d = R(1.0 / a.g.dx[AX]);
+  const int n = a.g.n[AX];
+  const int no = (AX == 1) ? a.g.n[2] : a.g.n[1];
+  const size_t lds = (size_t)2 * 5 * kTileP * kTileXP * sizeof(R);
+  dim3 grid((nx + kTileX - 1) / kTileX, (n + kTileA - 1) / kTileA, no);
+  hipLaunchKernelGGL((k_tile<R, S, AX, AX == 2>), grid, dim3(512), lds, st, a);
+}
+
+// kernel: 0 x-faces, 1 x boundary faces, 2 y-march, 3 z-march (+ combine),
+// 4 y-tile, 5 z-tile (+ combine)
 template <class R>
 hipError_t launch_face_kernel(int kernel, const StageArgs<R>& a, int scheme, int seg, hipStream_t st) {
 #define HYDRO_DISPATCH(S)                                  \
@@ -638,7 +809,9 @@ hipError_t launch_face_kernel(int kernel, const StageArgs<R>& a, int scheme, int
     case 0: launch_xface_t<R, S>(a, st); break;            \
     case 1: launch_xbound_t<R, S>(a, st); break;           \
     case 2: launch_march_t<R, S, 1>(a, seg, st); break;    \
-    default: launch_march_t<R, S, 2>(a, seg, st); break;   \
+    case 3: launch_march_t<R, S, 2>(a, seg, st); break;    \
+    case 4: launch_tile_t<R, S, 1>(a, st); break;          \
+    default: launch_tile_t<R, S, 2>(a, st); break;         \
   }
   if (scheme == kWenoJS) {
     HYDRO_DISPATCH(kWenoJS)

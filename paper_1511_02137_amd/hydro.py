@@ -24,8 +24,10 @@ DEPOSIT = {"ngp": 0, "gauss": 1}
 EXPORTED = [
     "hydro_default_config", "hydro_workspace_bytes", "hydro_init", "hydro_add_jet", "hydro_rk3_step",
     "hydro_primitives", "hydro_rhs", "hydro_sums", "hydro_get_state", "hydro_set_state", "hydro_diag",
-    "hydro_last_error", "hydro_destroy", "hydro_profile", "hydro_profile_read",
+    "hydro_last_error", "hydro_destroy", "hydro_profile", "hydro_profile_read", "hydro_set_option",
+    "hydro_get_option",
 ]
+OPT_YZ_KERNEL, OPT_MARCH_SEG = 0, 1
 KERNELS = ["xface", "xbound", "ymarch", "jet", "zmarch", "sums"]
 
 
@@ -95,9 +97,12 @@ def load_library(path: str = LIB_PATH):
     lib.hydro_destroy.argtypes = [vp]
     lib.hydro_destroy.restype = None
     lib.hydro_profile.argtypes = [vp, ctypes.c_int]
+    lib.hydro_set_option.argtypes = [vp, ctypes.c_int, ctypes.c_int]
+    lib.hydro_get_option.argtypes = [vp, ctypes.c_int, ctypes.POINTER(ctypes.c_int)]
     lib.hydro_profile_read.argtypes = [vp, dp, ctypes.POINTER(ctypes.c_int64), ctypes.c_int]
     for name in ("hydro_init", "hydro_add_jet", "hydro_rk3_step", "hydro_primitives", "hydro_rhs", "hydro_sums",
-                 "hydro_get_state", "hydro_set_state", "hydro_diag", "hydro_profile", "hydro_profile_read"):
+                 "hydro_get_state", "hydro_set_state", "hydro_diag", "hydro_profile", "hydro_profile_read",
+                 "hydro_set_option", "hydro_get_option"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -234,6 +239,14 @@ class Hydro:
         f = ctypes.c_int64(0)
         self._check(self.lib.hydro_diag(self.ctx, ctypes.byref(f)))
         return f.value
+
+    def set_option(self, option: int, value: int):
+        self._check(self.lib.hydro_set_option(self.ctx, int(option), int(value)))
+
+    def get_option(self, option: int) -> int:
+        v = ctypes.c_int(0)
+        self._check(self.lib.hydro_get_option(self.ctx, int(option), ctypes.byref(v)))
+        return v.value
 
     def profile(self, enable: bool = True):
         """Bracket every later launch of step() with HIP events on its stream."""

@@ -274,7 +274,7 @@ def test_fp32_form_against_fp64_at_full_size(n, njets):
     assert e_err <= 1e-5 and v_err <= 1e-5
     s32, s64 = h32.sums(), h64.sums()
     assert s32[5] == pytest.approx(s64[5], rel=1e-5)
-    assert s32[0] == pytest.approx(s64[0], rel=1e-6)
+    assert s32[0] == pytest.approx(s64[0], rel=1e-5)
 
 
 RHS_CASES = [
@@ -364,3 +364,20 @@ def test_paper_shape_256_sampled_cells_fp64():
         err = np.abs(got - ref) / Emax
         print("cell", (K, J, I), "max rel err %.2e" % err.max(), flush=True)
         assert np.all(err <= 1e-12), ((K, J, I), got, ref)
+
+
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+def test_kernel_variants_are_bitwise_identical(precision):
+    """y/z faces from LDS tiles or from register marches (any segment length)
+    use the same face arithmetic and accumulation order: identical bits."""
+    w = W.small_event(7, n=(45, 38, 70), steps=3)
+    outs = []
+    for yz, seg in ((0, 32), (1, 32), (1, 7), (1, 200)):
+        h = H().from_workload(w, precision=precision)
+        h.set_option(H().OPT_YZ_KERNEL, yz)
+        h.set_option(H().OPT_MARCH_SEG, seg)
+        h.step(3)
+        torch.cuda.synchronize()
+        outs.append(h.U.clone())
+    for u in outs[1:]:
+        assert torch.equal(outs[0], u)
