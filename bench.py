@@ -43,7 +43,19 @@ FLOPS_PER_CELL = {
     "zmarch": 1550 + 25 + 10 + 15,
 }
 FLOPS_PER_CELL_UPDATE = sum(FLOPS_PER_CELL.values())  # 4795
+# Algorithmic words moved per cell by each kernel (W read + D read/write;
+# z: + U^n read in stages 2-3 (2/3 on average) + output write).
+BYTES_PER_CELL = {"xface": 10, "ymarch": 15, "zmarch": 5 + 5 + 5 * 2 / 3 + 5}
 PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3}  # MI355X vector FP64 / FP32 (packed)
+
+# HBM bytes per launch from rocprofv3 FETCH_SIZE / WRITE_SIZE runs (KiB per
+# dispatch, scaled by a 1 GiB plain copy: read x2.0, write x1.0), for the
+# kernel source with the given hash; reported as null once the source changes.
+# Source: profiles/stage_256cube_f64.md.
+MEASURED_TRAFFIC = {
+    ("zmarch", "f64", "tile", 256): {"kernels_sha256": "728d4b5e8f55d3ef",
+                                     "read_bytes": 893500 * 2.0 * 1024, "write_bytes": 655400 * 1.0 * 1024},
+}
 
 
 def cpu_baseline(w, target_s: float):
@@ -138,8 +150,16 @@ def main():
     t_launch = prof[dom][0] / prof[dom][1]
     achieved = FLOPS_PER_CELL[dom] * nc / (t_launch * 1e-3) / 1e12
     peak = PEAK_TFLOPS[args.precision]
+    traffic = None
+    rec = MEASURED_TRAFFIC.get((dom, args.precision, args.yz, args.n))
+    if rec is not None:
+        import hashlib
+        src = os.path.join(ROOT, "paper_1511_02137_amd", "csrc", "hydro_kernels.hip")
+        if hashlib.sha256(open(src, "rb").read()).hexdigest()[:16] == rec["kernels_sha256"]:
+            traffic = rec["read_bytes"] + rec["write_bytes"]
     roofline = {"bound": "alu", "kernel": dom, "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
-                "frac": achieved / peak, "traffic": None,
+                "frac": achieved / peak, "traffic": traffic,
+                "algorithmic_bytes": BYTES_PER_CELL[dom] * (8 if args.precision == "f64" else 4) * nc,
                 "flops_per_cell": FLOPS_PER_CELL[dom]}
     step_frac = FLOPS_PER_CELL_UPDATE * value / 1e12 / peak
 
