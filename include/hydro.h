@@ -160,6 +160,43 @@ int hydro_set_state(hydro_ctx* ctx, int64_t step, const double* E_jet, int n_jet
 /* Synchronous: number of conserved->primitive fix-ups so far. */
 int hydro_diag(hydro_ctx* ctx, int64_t* fixups);
 
+/* Synchronous: set U from primitive fields prim0 (device FP64, as in
+ * hydro_init) and restart the context: step 0, jet energies E0, ledger 0. */
+int hydro_reset(hydro_ctx* ctx, const double* prim0, void* U, void* stream);
+
+/* Replace the parameters of jet `id` (synchronous; same checks as
+ * hydro_add_jet; E0 resets the jet's remaining energy). */
+int hydro_set_jet(hydro_ctx* ctx, int id, const hydro_jet* jet);
+
+/* The energy-weighted anisotropy on the z = 0 plane,
+ *   eps2 = sum (y^2 - x^2) e / sum (y^2 + x^2) e,
+ * e the rest-frame energy density (mean of the two middle planes for even
+ * nz, the middle plane for odd nz), x and y cell centres from the grid
+ * origin.  eps2_out: device double (may be NULL).  If seed is not NULL it
+ * receives scale * d eps2 / dU (device, layout and type of U, zero off the
+ * z = 0 planes). */
+int hydro_loss_eps2(hydro_ctx* ctx, const void* U, double* eps2_out, void* seed, double scale, void* stream);
+
+/* Reverse sweep (hand-written adjoint) over the nsteps SSP-RK3 steps that
+ * start from the checkpoint U_ckpt taken at step index step0 with jet
+ * energies E_jet0 (host [n_jet]; may be NULL without jets).  On entry
+ * lambda (device, layout and type of U) holds dJ/dU at step step0 + nsteps,
+ * on exit dJ/dU at step0.  grad_jets (device FP64 [n_jet][5]: d/dkappa_rad,
+ * d/dkappa_coll, d/dx0, d/dy0, d/dz0; origin derivatives are zero for the
+ * NGP deposit) is incremented in FP64.  The stage states of the segment are
+ * recomputed into the workspace, which must have been sized with
+ * hydro_workspace_bytes(cfg, adjoint_k >= nsteps); each axis must fit the
+ * line adjoint's LDS tile ((24 n + 304) words <= 64 KiB: n <= 328 in FP64,
+ * n <= 670 in FP32), else HYDRO_EINVAL.  The
+ * context's U, step, jet energies and ledger are left unchanged. */
+int hydro_adjoint_step(hydro_ctx* ctx, const void* U_ckpt, int64_t step0, const double* E_jet0, int nsteps,
+                       void* lambda, double* grad_jets, void* stream);
+
+/* Adjoint of the primitive->conserved map of hydro_init at prim0 (device
+ * FP64 [5][nz][ny][nx]): grad_prim (device FP64, same layout) =
+ * (dU/dprim)^T lambda, i.e. d/de, d/dvx, d/dvy, d/dvz, d/dn. */
+int hydro_init_vjp(hydro_ctx* ctx, const double* prim0, const void* lambda, double* grad_prim, void* stream);
+
 /* Launch-shape options of a context (results do not depend on them: every
  * variant computes each face with the same arithmetic). */
 typedef enum {
@@ -179,7 +216,8 @@ typedef enum {
   HYDRO_K_JET = 3,     /* jet source */
   HYDRO_K_ZMARCH = 4,  /* z-faces (LDS tiles or marches along z) and the RK combine */
   HYDRO_K_SUMS = 5,    /* FP64 conservation sums */
-  HYDRO_NK = 6
+  HYDRO_K_ADJ = 6,     /* line adjoint kernels of one axis (hydro_adjoint_step) */
+  HYDRO_NK = 7
 } hydro_kernel_class;
 
 /* Diagnostics: with enable != 0, every later launch of hydro_rk3_step is

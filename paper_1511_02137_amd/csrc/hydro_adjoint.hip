@@ -1,0 +1,888 @@
+// hydro_adjoint.hip -- reverse mode (vector-Jacobian products) of one SSP-RK3
+// stage, of the jet source, of the anisotropy observable eps2 and of the
+// primitive->conserved map of the initial state.
+//
+// For a stage  Y = a U^n + b (W + dt L(W)),  L = D + S, the reverse sweep
+// needs G = (dL/dW)^T lambda_Y.  D's part goes face by face:
+//   phi(face i+1/2) = (lambda_{i+1} - lambda_i)/dx       (face adjoint)
+//   -> reverse of F(i+1/2) = R_L(F+_{i-3..i+3}) + R_L(F-_{i+4..i-2})
+//   -> adjoints of the split fluxes at each point
+//   -> (F+- = (f +- W)/2, f through the FP64 conserved->primitive recovery)
+//   -> adjoint of W at the point; ghost points pass theirs to the cell they copy.
+// A workgroup owns a whole line along the axis, so every face that touches a
+// cell of the line is handled in the same workgroup: each lane reverses its
+// face, writes the seven partials to LDS, and each lane gathers the partials
+// of its own point in a fixed order (deterministic, no atomics).
+
+#include <hip/hip_runtime.h>
+
+#include "hydro_device.hpp"
+#include "hydro_internal.hpp"
+
+namespace hydro {
+
+// ---------------------------------------------------------------------------
+// Conserved -> primitive with its derivatives (FP64).  Without fix-up:
+// s = sqrt(4E^2 - 3M^2), e = s - E (evaluated as 3(E^2 - M^2)/(E + s)),
+// de/dE = 4E/s - 1, de/dM_j = -3 M_j/s, v = M/(E + e/3).
+struct PrimJ {
+  double E;
+  double e, v[3], iW;  // values; iW = 1/(E + p) = 1/(E + e/3)
+  double eE, eM[3];    // de/dE, de/dM_j (at the possibly rescaled M)
+  double Mc[3];        // M used in the recovery (rescaled when capped)
+  double Mh[3];        // M/|M| (cap)
+  double capf;         // (1 - 1e-10) E / |M| (cap)
+  bool vac, cap;
+};
+
+__device__ __forceinline__ PrimJ c2p_jac(double E, double Mx, double My, double Mz) {
+  PrimJ J;
+  J.E = E;
+  J.vac = false;
+  J.cap = false;
+  J.capf = 1.0;
+  double M[3] = {Mx, My, Mz};
+  if (E <= kEFloor) {
+    J.vac = true;
+    J.e = kEFloor;
+    J.iW = 1.0 / (kEFloor + kEFloor / 3.0);
+    for (int k = 0; k < 3; ++k) {
+      J.v[k] = 0.0;
+      J.eM[k] = 0.0;
+      J.Mc[k] = 0.0;
+      J.Mh[k] = 0.0;
+    }
+    J.eE = 0.0;
+    return J;
+  }
+  double M2 = M[0] * M[0] + M[1] * M[1] + M[2] * M[2];
+  if (M2 >= kVCap * kVCap * E * E) {
+    J.cap = true;
+    const double inrm = 1.0 / sqrt(M2);
+    const double sc = kVCap * E * inrm;
+    J.capf = sc;
+    for (int k = 0; k < 3; ++k) {
+      J.Mh[k] = M[k] * inrm;
+      M[k] = M[k] * sc;
+    }
+    M2 = M[0] * M[0] + M[1] * M[1] + M[2] * M[2];
+  }
+  const double s = sqrt(4.0 * E * E - 3.0 * M2);
+  const double is = 1.0 / s;
+  const double e = 3.0 * (E * E - M2) / (E + s);
+  J.e = e;
+  J.iW = 1.0 / (E + e * (1.0 / 3.0));
+  for (int k = 0; k < 3; ++k) {
+    J.Mc[k] = M[k];
+    J.v[k] = M[k] * J.iW;
+    J.eM[k] = -3.0 * M[k] * is;
+  }
+  J.eE = 4.0 * E * is - 1.0;
+  return J;
+}
+
+// Given adjoints eb of e and vb of v, the adjoints of (E, M):
+// with Q = (vb . v)/(E + p) and kappa = eb - Q/3:
+//   Eb = kappa de/dE - Q,  Mb_k = kappa de/dM_k + vb_k/(E + p),
+// then through the velocity cap M' = c M, c = (1 - 1e-10) E/|M|.
+__device__ __forceinline__ void c2p_vjp(const PrimJ& J, double eb, const double vb[3], double& Eb, double Mb[3]) {
+  if (J.vac) {
+    Eb = 0.0;
+    Mb[0] = Mb[1] = Mb[2] = 0.0;
+    return;
+  }
+  const double Q = (vb[0] * J.v[0] + vb[1] * J.v[1] + vb[2] * J.v[2]) * J.iW;
+  const double kap = eb - Q * (1.0 / 3.0);
+  double Ebp = kap * J.eE - Q;
+  double Mbp[3];
+  for (int k = 0; k < 3; ++k) Mbp[k] = kap * J.eM[k] + vb[k] * J.iW;
+  if (!J.cap) {
+    Eb = Ebp;
+    for (int k = 0; k < 3; ++k) Mb[k] = Mbp[k];
+    return;
+  }
+  const double dM = Mbp[0] * J.Mc[0] + Mbp[1] * J.Mc[1] + Mbp[2] * J.Mc[2];
+  const double dh = Mbp[0] * J.Mh[0] + Mbp[1] * J.Mh[1] + Mbp[2] * J.Mh[2];
+  Eb = Ebp + dM / J.E;
+  for (int k = 0; k < 3; ++k) Mb[k] = J.capf * (Mbp[k] - J.Mh[k] * dh);
+}
+
+// Adjoint of the split fluxes at one point (axis AX): ap, am are the adjoints
+// of F+ and F-; returns the adjoint of the conserved W of that point.
+template <class R, int AX>
+__device__ __forceinline__ void split_flux_vjp(const R u[5], const PrimJ& J, const double ap[5], const double am[5],
+                                               double ub[5]) {
+  double fb[5];
+  for (int c = 0; c < 5; ++c) {
+    fb[c] = 0.5 * (ap[c] + am[c]);
+    ub[c] = 0.5 * (ap[c] - am[c]);
+  }
+  const double vd = (double)(R)J.v[AX];
+  ub[1 + AX] += fb[0];
+  double vbd = 0.0;
+  for (int j = 0; j < 3; ++j) {
+    ub[1 + j] += fb[1 + j] * vd;
+    vbd += fb[1 + j] * (double)u[1 + j];
+  }
+  ub[4] += fb[4] * vd;
+  vbd += fb[4] * (double)u[4];
+  const double pb = fb[1 + AX];
+  double vb[3] = {0.0, 0.0, 0.0};
+  vb[AX] = vbd;
+  double Eb, Mb[3];
+  c2p_vjp(J, pb / 3.0, vb, Eb, Mb);
+  ub[0] += Eb;
+  for (int k = 0; k < 3; ++k) ub[1 + k] += Mb[k];
+}
+
+// ---------------------------------------------------------------------------
+// Reverse mode of weno7: ab[m] = phi * dR/da_m for the reconstruction of
+// a0..a6 (same forward arithmetic: differences, candidates d_k (q_k - a3),
+// smoothness from differences, Z or JS weights, R = a3 + sum w r / sum w d),
+// then the chain back through weights, smoothness indicators, candidates and
+// differences.  Every multiply-add is an explicit fma.
+template <class R, int S>
+__device__ __forceinline__ void weno7_vjp(const R* a, R phi, R eps, R* ab) {
+  const R e0 = a[1] - a[0], e1 = a[2] - a[1], e2 = a[3] - a[2], e3 = a[4] - a[3], e4 = a[5] - a[4],
+          e5 = a[6] - a[5];
+  R eb[6], fb[5], gb[4];
+  R rb0, rb1, rb2, rb3;
+  if (S == kWenoLinear) {
+    rb0 = rb1 = rb2 = rb3 = phi;
+#pragma unroll
+    for (int k = 0; k < 6; ++k) eb[k] = R(0);
+#pragma unroll
+    for (int k = 0; k < 5; ++k) fb[k] = R(0);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) gb[k] = R(0);
+  } else {
+    const R r0 = fma(R(13.0 / 420.0), e2, fma(R(-10.0 / 420.0), e1, R(3.0 / 420.0) * e0));
+    const R r1 = fma(R(3.0 / 35.0), e3, fma(R(4.0 / 35.0), e2, R(-1.0 / 35.0) * e1));
+    const R r2 = fma(R(-3.0 / 70.0), e4, fma(R(18.0 / 70.0), e3, R(3.0 / 70.0) * e2));
+    const R r3 = fma(R(1.0 / 105.0), e5, fma(R(-4.0 / 105.0), e4, R(9.0 / 105.0) * e3));
+    const R f[5] = {e1 - e0, e2 - e1, e3 - e2, e4 - e3, e5 - e4};
+    const R g[4] = {f[1] - f[0], f[2] - f[1], f[3] - f[2], f[4] - f[3]};
+    const R e[4] = {e0, e1, e2, e3};
+    const R hk[4] = {R(2.5), R(1.5), R(0.5), R(-0.5)};
+    const R mk[4] = {R(11.0 / 6.0), R(1.0 / 3.0), R(-1.0 / 6.0), R(1.0 / 3.0)};
+    const R gk[4] = {R(2), R(1), R(0), R(-1)};
+    R b[4], sk[4], ck[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      sk[k] = fma(mk[k], g[k], fma(hk[k], f[k], e[k]));
+      ck[k] = fma(gk[k], g[k], f[k]);
+      b[k] = fma(sk[k], sk[k], fma(R(13.0 / 12.0) * ck[k], ck[k], fma(R(781.0 / 720.0) * g[k], g[k], eps)));
+    }
+    R iv[4];
+    if (sizeof(R) == 8) {
+      const R p01 = b[0] * b[1], p23 = b[2] * b[3];
+      const R inv = (R)rcp_nr((double)(p01 * p23));
+      const R u23 = inv * p23, u01 = inv * p01;
+      iv[0] = u23 * b[1];
+      iv[1] = u23 * b[0];
+      iv[2] = u01 * b[3];
+      iv[3] = u01 * b[2];
+    } else {
+#pragma unroll
+      for (int k = 0; k < 4; ++k) iv[k] = rcp_approx<R>(b[k]);
+    }
+    R w[4], s[4];
+    R sg = R(1);
+    if (S == kWenoZ) {
+      const R traw = fma(R(3), b[1] - b[2], b[0] - b[3]);
+      sg = traw < R(0) ? R(-1) : R(1);
+      const R tau = sg * traw;
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        s[k] = tau * iv[k];
+        w[k] = fma(s[k], s[k], R(1));
+      }
+    } else {
+#pragma unroll
+      for (int k = 0; k < 4; ++k) w[k] = iv[k] * iv[k];
+    }
+    const R dk[4] = {R(1.0 / 35.0), R(12.0 / 35.0), R(18.0 / 35.0), R(4.0 / 35.0)};
+    const R den = fma(w[3], dk[3], fma(w[2], dk[2], fma(w[1], dk[1], w[0] * dk[0])));
+    const R num = fma(w[3], r3, fma(w[2], r2, fma(w[1], r1, w[0] * r0)));
+    const R invd = sizeof(R) == 8 ? (R)rcp_nr((double)den) : rcp_approx<R>(den);
+    const R corr = num * invd;
+    const R pin = phi * invd;
+    rb0 = pin * w[0];
+    rb1 = pin * w[1];
+    rb2 = pin * w[2];
+    rb3 = pin * w[3];
+    const R rr[4] = {r0, r1, r2, r3};
+    R bb[4];
+    R taub = R(0);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const R wb = pin * fma(-dk[k], corr, rr[k]);  // dR/dw_k
+      if (S == kWenoZ) {
+        const R t = (wb + wb) * (s[k] * iv[k]);      // dR/dtau through w_k
+        bb[k] = -t * s[k];
+        taub = taub + t;
+      } else {
+        bb[k] = R(-2) * wb * (w[k] * iv[k]);
+      }
+    }
+    if (S == kWenoZ) {
+      const R t = sg * taub;
+      bb[0] = bb[0] + t;
+      bb[1] = fma(R(3), t, bb[1]);
+      bb[2] = fma(R(-3), t, bb[2]);
+      bb[3] = bb[3] - t;
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const R sb = R(2) * sk[k] * bb[k];
+      const R cb = R(13.0 / 6.0) * ck[k] * bb[k];
+      eb[k] = sb;
+      fb[k] = fma(hk[k], sb, cb);
+      gb[k] = fma(mk[k], sb, fma(gk[k], cb, R(781.0 / 360.0) * g[k] * bb[k]));
+    }
+    eb[4] = R(0);
+    eb[5] = R(0);
+    fb[4] = R(0);
+  }
+  // candidates r_k(e)
+  eb[0] = fma(R(3.0 / 420.0), rb0, eb[0]);
+  eb[1] = fma(R(-1.0 / 35.0), rb1, fma(R(-10.0 / 420.0), rb0, eb[1]));
+  eb[2] = fma(R(3.0 / 70.0), rb2, fma(R(4.0 / 35.0), rb1, fma(R(13.0 / 420.0), rb0, eb[2])));
+  eb[3] = fma(R(9.0 / 105.0), rb3, fma(R(18.0 / 70.0), rb2, fma(R(3.0 / 35.0), rb1, eb[3])));
+  eb[4] = fma(R(-4.0 / 105.0), rb3, fma(R(-3.0 / 70.0), rb2, eb[4]));
+  eb[5] = fma(R(1.0 / 105.0), rb3, eb[5]);
+  // second differences g_j = f_{j+1} - f_j, first f_j = e_{j+1} - e_j, e_j = a_{j+1} - a_j
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    fb[j + 1] = fb[j + 1] + gb[j];
+    fb[j] = fb[j] - gb[j];
+  }
+#pragma unroll
+  for (int j = 0; j < 5; ++j) {
+    eb[j + 1] = eb[j + 1] + fb[j];
+    eb[j] = eb[j] - fb[j];
+  }
+  ab[0] = -eb[0];
+#pragma unroll
+  for (int j = 1; j < 6; ++j) ab[j] = eb[j - 1] - eb[j];
+  ab[6] = eb[5];
+  ab[3] = ab[3] + phi;
+}
+
+// ---------------------------------------------------------------------------
+// Line adjoint along axis AX: one workgroup per line (blockDim >= n, <= 1024).
+// G (first: =, else +=) receives (dD_AX/dW)^T mu for the faces -1/2..n-3/2
+// of the line (periodic: face -1/2 is also the right face of cell n-1); the
+// outflow face n-1/2 is added by k_bound_adj.
+__device__ __forceinline__ long long line_base(int AX, long long L, const Grid& g, long long& stride) {
+  const int nx = g.n[0], ny = g.n[1];
+  if (AX == 0) {
+    stride = 1;
+    return L * nx;
+  }
+  if (AX == 1) {
+    stride = nx;
+    const long long x = L % nx, z = L / nx;
+    return z * (long long)nx * ny + x;
+  }
+  stride = (long long)nx * ny;
+  const long long x = L % nx, y = L / nx;
+  return y * nx + x;
+}
+
+__device__ __forceinline__ long long n_lines(int AX, const Grid& g) {
+  return AX == 0 ? (long long)g.n[1] * g.n[2] : (AX == 1 ? (long long)g.n[0] * g.n[2] : (long long)g.n[0] * g.n[1]);
+}
+
+// Block order: consecutive lines (neighbours in memory for the y/z axes) go
+// to the same XCD (blocks are dealt round-robin over the 8 XCDs).
+__device__ __forceinline__ long long xcd_line(long long nlines) {
+  const long long per = (nlines + 7) / 8;
+  return (long long)(blockIdx.x % 8) * per + blockIdx.x / 8;
+}
+
+template <class R, int S, int AX, int TBMAX>
+__global__ void __launch_bounds__(TBMAX) k_line_adj(AdjArgs<R> a) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  R* s = reinterpret_cast<R*>(smem_raw);
+  const long long nlines = n_lines(AX, a.g);
+  const long long L = xcd_line(nlines);
+  if (L >= nlines) return;  // whole workgroup
+  const int n = a.g.n[AX];
+  const int bc = a.g.bc[AX];
+  const int P = n + 8;
+  const int Q = n + 16;
+  const long long nc = a.g.nc;
+  long long stride;
+  const long long base = line_base(AX, L, a.g, stride);
+  R* sFp = s;               // [5][P]
+  R* sFm = s + 5 * P;       // [5][P]
+  R* sX = s + 10 * P;       // [2][7][Q]; first used to stage mu [5][n]
+  const int tid = threadIdx.x;
+  const int TB = blockDim.x;
+  unsigned fix = 0;
+
+  // points: lane handles t = tid and t = tid + TB (slot j = padded index + 4)
+  int slot[2] = {-1, -1};
+  R uo[2][5];
+#pragma unroll
+  for (int q = 0; q < 2; ++q) {
+    const int t = tid + q * TB;
+    if (t < n + 8) {
+      const int j = (t < n) ? t + 4 : (t < n + 4 ? t - n : t);
+      slot[q] = j;
+      const int src = map_idx(j - 4, n, bc);
+      load5(a.W, nc, base + (long long)src * stride, uo[q]);
+      const PrimV pv = c2p(uo[q], fix);
+      R Fp[5], Fm[5];
+      split_flux<R, AX>(uo[q], pv, Fp, Fm);
+#pragma unroll
+      for (int c = 0; c < 5; ++c) {
+        sFp[c * P + j] = Fp[c];
+        sFm[c * P + j] = Fm[c];
+      }
+    }
+  }
+  R my[5];  // mu of the lane's own cell (used by the fused combine)
+  if (tid < n) {
+#pragma unroll
+    for (int c = 0; c < 5; ++c) {
+      my[c] = a.mu[c * nc + base + (long long)tid * stride];
+      sX[c * n + tid] = my[c];
+    }
+  }
+  __syncthreads();
+  // face adjoints phi(x - 1/2) = (mu(x) - mu(x-1)) / dx
+  R phi[5];
+  if (tid < n) {
+#pragma unroll
+    for (int c = 0; c < 5; ++c) {
+      const R left = tid > 0 ? sX[c * n + tid - 1] : (bc ? sX[c * n + n - 1] : R(0));
+      phi[c] = (sX[c * n + tid] - left) * a.inv_d;
+    }
+  }
+  __syncthreads();
+  for (int z = tid; z < 14 * 16; z += TB) {  // pads: 8 below and 8 above each row
+    const int row = z >> 4, k = z & 15;
+    sX[row * Q + (k < 8 ? k : n + k)] = R(0);
+  }
+
+  R acc[2][2][5];  // [point][split][field]
+#pragma unroll
+  for (int c = 0; c < 5; ++c) {
+    if (tid < n) {
+      R args[7], ab[7];
+#pragma unroll
+      for (int m = 0; m < 7; ++m) args[m] = sFp[c * P + tid + m];
+      weno7_vjp<R, S>(args, phi[c], a.eps, ab);
+#pragma unroll
+      for (int m = 0; m < 7; ++m) sX[m * Q + tid + 8] = ab[m];
+#pragma unroll
+      for (int m = 0; m < 7; ++m) args[m] = sFm[c * P + tid + 7 - m];
+      weno7_vjp<R, S>(args, phi[c], a.eps, ab);
+#pragma unroll
+      for (int m = 0; m < 7; ++m) sX[(7 + m) * Q + tid + 8] = ab[m];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      const int j = slot[q];
+      R sp = R(0), sm = R(0);
+      if (j >= 0) {
+        // slot j is argument m of face j - m (F+) and of face j - 7 + m (F-)
+#pragma unroll
+        for (int m = 0; m < 7; ++m) {
+          sp = sp + sX[m * Q + j - m + 8];
+          sm = sm + sX[(7 + m) * Q + j - 7 + m + 8];
+        }
+      }
+      acc[q][0][c] = sp;
+      acc[q][1][c] = sm;
+    }
+    __syncthreads();
+  }
+
+  // split-flux adjoint -> adjoint of W at the point; own cells to LDS, ghosts after
+  R* sW = s;            // [5][n]   (reuses sFp)
+  R* sGh = s + 5 * n;   // [5][8]
+#pragma unroll
+  for (int q = 0; q < 2; ++q) {
+    const int j = slot[q];
+    if (j < 0) continue;
+    const PrimJ J = c2p_jac((double)uo[q][0], (double)uo[q][1], (double)uo[q][2], (double)uo[q][3]);
+    double ap[5], am[5], ub[5];
+#pragma unroll
+    for (int c = 0; c < 5; ++c) {
+      ap[c] = (double)acc[q][0][c];
+      am[c] = (double)acc[q][1][c];
+    }
+    split_flux_vjp<R, AX>(uo[q], J, ap, am, ub);
+    if (j >= 4 && j < n + 4) {
+      for (int c = 0; c < 5; ++c) sW[c * n + j - 4] = (R)ub[c];
+    } else {
+      const int gslot = j < 4 ? j : j - n;  // 0..7
+      for (int c = 0; c < 5; ++c) sGh[c * 8 + gslot] = (R)ub[c];
+    }
+  }
+  __syncthreads();
+  if (tid == 0) {
+    for (int gslot = 0; gslot < 8; ++gslot) {
+      const int j = gslot < 4 ? gslot : gslot + n;
+      const int cell = map_idx(j - 4, n, bc);
+      for (int c = 0; c < 5; ++c) sW[c * n + cell] = sW[c * n + cell] + sGh[c * 8 + gslot];
+    }
+  }
+  __syncthreads();
+  if (tid < n) {
+    const long long cell = base + (long long)tid * stride;
+#pragma unroll
+    for (int c = 0; c < 5; ++c) {
+      const long long q = c * nc + cell;
+      const R gv = a.first ? sW[c * n + tid] : a.G[q] + sW[c * n + tid];
+      if (a.stage == 0) {
+        a.G[q] = gv;
+      } else {
+        const R t = fma(a.dt, gv, my[c]);
+        if (a.stage == 3) {
+          a.lW[q] = R(2.0 / 3.0) * t;
+          a.acc[q] = R(1.0 / 3.0) * my[c];
+        } else if (a.stage == 2) {
+          a.lW[q] = R(0.25) * t;
+          a.acc[q] = fma(R(0.75), my[c], a.acc[q]);
+        } else {
+          a.lW[q] = a.acc[q] + t;
+        }
+      }
+    }
+  }
+  add_fixups(a.fixups, fix);
+}
+
+// Outflow face n-1/2 of every line along AX: phi = -mu(n-1)/dx.  One lane per
+// line; the adjoints of its eight stencil points (ghosts -> cell n-1) are
+// added to G in a fixed order.
+template <class R, int S, int AX>
+__global__ void __launch_bounds__(64) k_bound_adj(AdjArgs<R> a) {
+  __shared__ double sA[64][8][10];
+  const long long nlines = n_lines(AX, a.g);
+  const long long L = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const int n = a.g.n[AX];
+  const long long nc = a.g.nc;
+  const int tl = threadIdx.x;
+  if (L >= nlines) return;  // no barriers below
+  long long stride;
+  const long long base = line_base(AX, L, a.g, stride);
+  unsigned fix = 0;
+  for (int m = 0; m < 8; ++m)
+    for (int k = 0; k < 10; ++k) sA[tl][m][k] = 0.0;
+  for (int c = 0; c < 5; ++c) {
+    R fp[8], fm[8];
+    for (int m = 0; m < 8; ++m) {
+      R u[5];
+      load5(a.W, nc, base + (long long)map_idx(n - 4 + m, n, 0) * stride, u);
+      const PrimV pv = c2p(u, fix);
+      R Fp[5], Fm[5];
+      split_flux<R, AX>(u, pv, Fp, Fm);
+      fp[m] = Fp[c];
+      fm[m] = Fm[c];
+    }
+    const R phi = -a.mu[c * nc + base + (long long)(n - 1) * stride] * a.inv_d;
+    R args[7], ab[7];
+    for (int m = 0; m < 7; ++m) args[m] = fp[m];
+    weno7_vjp<R, S>(args, phi, a.eps, ab);
+    for (int m = 0; m < 7; ++m) sA[tl][m][c] += (double)ab[m];
+    for (int m = 0; m < 7; ++m) args[m] = fm[7 - m];
+    weno7_vjp<R, S>(args, phi, a.eps, ab);
+    for (int m = 0; m < 7; ++m) sA[tl][7 - m][5 + c] += (double)ab[m];
+  }
+  for (int m = 0; m < 8; ++m) {
+    const int cell = map_idx(n - 4 + m, n, 0);
+    R u[5];
+    load5(a.W, nc, base + (long long)cell * stride, u);
+    const PrimJ J = c2p_jac((double)u[0], (double)u[1], (double)u[2], (double)u[3]);
+    double ap[5], am[5], ub[5];
+    for (int c = 0; c < 5; ++c) {
+      ap[c] = sA[tl][m][c];
+      am[c] = sA[tl][m][5 + c];
+    }
+    split_flux_vjp<R, AX>(u, J, ap, am, ub);
+    for (int c = 0; c < 5; ++c) {
+      R* gp = a.G + c * nc + base + (long long)cell * stride;
+      *gp = *gp + (R)ub[c];
+    }
+  }
+  add_fixups(a.fixups, fix);
+}
+
+// ---------------------------------------------------------------------------
+// Jet source adjoint: G += (dS/dW)^T mu at the deposit cells, and
+// grad[j] += bdt * (dS/dtheta)^T mu for theta = (kappa_rad, kappa_coll, x0, y0, z0).
+template <class R>
+__global__ void __launch_bounds__(512) k_jet_adj(JetAdjArgs a) {
+  const R* W = static_cast<const R*>(a.W);
+  const R* mu = static_cast<const R*>(a.mu);
+  R* G = static_cast<R*>(a.G);
+  const long long nc = a.g.nc;
+  const double dV = a.g.dx[0] * a.g.dx[1] * a.g.dx[2];
+  const double hc = a.hbarc;
+  __shared__ double red[12][512];
+  __shared__ double wax[3][7], dwax[3][7];
+  __shared__ int ctr_s[3];
+  __shared__ int inside_s;
+  const int t = threadIdx.x;
+  for (int j = 0; j < a.njet; ++j) {
+    const JetDev jt = a.s->jets[j];
+    const bool chi = a.Ehist[j] > 0.0;
+    const double ell = a.t - jt.t_start;
+    if (t == 0) {
+      int in = (chi && ell >= 0.0) ? 1 : 0;
+      for (int d = 0; d < 3; ++d) {
+        const double x = jt.x0[d] + jt.dir[d] * ell;
+        const int c = ngp_index(x, a.g.n[d], a.g.dx[d]);
+        ctr_s[d] = c;
+        if (c < 0) in = 0;
+        if (a.deposit == 1) {
+          const double sig2 = a.g.dx[d] * a.g.dx[d];
+          double sum = 0.0, dsum = 0.0;
+          for (int m = 0; m < 7; ++m) {
+            const double del = cell_centre(c - 3 + m, a.g.n[d], a.g.dx[d]) - x;
+            wax[d][m] = exp(-(del * del) / (2.0 * sig2));
+            sum = sum + wax[d][m];
+          }
+          for (int m = 0; m < 7; ++m) wax[d][m] = wax[d][m] / sum;
+          for (int m = 0; m < 7; ++m) {
+            const double del = cell_centre(c - 3 + m, a.g.n[d], a.g.dx[d]) - x;
+            dsum += wax[d][m] * del / sig2;
+          }
+          for (int m = 0; m < 7; ++m) {
+            const double del = cell_centre(c - 3 + m, a.g.n[d], a.g.dx[d]) - x;
+            dwax[d][m] = wax[d][m] * (del / sig2 - dsum);  // d w_m / d x
+          }
+        }
+      }
+      inside_s = in;
+    }
+    __syncthreads();
+    if (inside_s) {
+      if (a.deposit == 0) {
+        if (t == 0) {
+          const long long cell = ((long long)ctr_s[2] * a.g.n[1] + ctr_s[1]) * a.g.n[0] + ctr_s[0];
+          const PrimJ J = c2p_jac((double)W[cell], (double)W[nc + cell], (double)W[2 * nc + cell],
+                                  (double)W[3 * nc + cell]);
+          const double T = temperature(J.e, a.eos_dof, hc);
+          const double sig = ((double)mu[cell] + jt.dir[0] * (double)mu[nc + cell] +
+                              jt.dir[1] * (double)mu[2 * nc + cell] + jt.dir[2] * (double)mu[3 * nc + cell]) / dV;
+          const double dPdT = 2.0 * jt.kappa_coll * jt.crcf * T / hc + 3.0 * jt.kappa_rad * jt.crcf * T * T * ell / (hc * hc);
+          const double eb = sig * dPdT * T / (4.0 * J.e);
+          const double vb[3] = {0.0, 0.0, 0.0};
+          double Eb, Mb[3];
+          c2p_vjp(J, eb, vb, Eb, Mb);
+          G[cell] = G[cell] + (R)Eb;
+          for (int k = 0; k < 3; ++k) G[(1 + k) * nc + cell] = G[(1 + k) * nc + cell] + (R)Mb[k];
+          double* gr = a.grad + 5 * j;
+          gr[0] += a.bdt * sig * jt.crcf * T * T * T * ell / (hc * hc);
+          gr[1] += a.bdt * sig * jt.crcf * T * T / hc;
+        }
+      } else {
+        // 7^3 footprint, thread t < 343
+        double w = 0.0, T = 0.0, sig = 0.0, dw[3] = {0.0, 0.0, 0.0};
+        long long cell = -1;
+        PrimJ J;
+        if (t < 343) {
+          const int mi = t % 7, mj = (t / 7) % 7, mk = t / 49;
+          const int i = ctr_s[0] - 3 + mi, jj = ctr_s[1] - 3 + mj, k = ctr_s[2] - 3 + mk;
+          if (i >= 0 && i < a.g.n[0] && jj >= 0 && jj < a.g.n[1] && k >= 0 && k < a.g.n[2]) {
+            cell = ((long long)k * a.g.n[1] + jj) * a.g.n[0] + i;
+            w = wax[0][mi] * wax[1][mj] * wax[2][mk];
+            dw[0] = dwax[0][mi] * wax[1][mj] * wax[2][mk];
+            dw[1] = wax[0][mi] * dwax[1][mj] * wax[2][mk];
+            dw[2] = wax[0][mi] * wax[1][mj] * dwax[2][mk];
+            J = c2p_jac((double)W[cell], (double)W[nc + cell], (double)W[2 * nc + cell], (double)W[3 * nc + cell]);
+            T = temperature(J.e, a.eos_dof, hc);
+            sig = ((double)mu[cell] + jt.dir[0] * (double)mu[nc + cell] + jt.dir[1] * (double)mu[2 * nc + cell] +
+                   jt.dir[2] * (double)mu[3 * nc + cell]) / dV;
+          }
+        }
+        // reductions: 0 wsum, 1 sum wT, 2 sum sig w, 3-5 sum sig dw, 6-8 sum dw T, 9-11 sum dw
+        const double vals[12] = {w, w * T, sig * w, sig * dw[0], sig * dw[1], sig * dw[2],
+                                 dw[0] * T, dw[1] * T, dw[2] * T, dw[0], dw[1], dw[2]};
+        for (int r = 0; r < 12; ++r) red[r][t] = vals[r];
+        __syncthreads();
+        for (int h = 256; h > 0; h >>= 1) {
+          if (t < h)
+            for (int r = 0; r < 12; ++r) red[r][t] = red[r][t] + red[r][t + h];
+          __syncthreads();
+        }
+        const double wsum = red[0][0];
+        const double Tj = red[1][0] / wsum;
+        const double Pj = energy_loss(jt, Tj, ell, hc);
+        const double dJdP = red[2][0];
+        const double dPdT = 2.0 * jt.kappa_coll * jt.crcf * Tj / hc + 3.0 * jt.kappa_rad * jt.crcf * Tj * Tj * ell / (hc * hc);
+        const double dJdT = dJdP * dPdT;
+        if (cell >= 0) {
+          const double eb = dJdT * (w / wsum) * T / (4.0 * J.e);
+          const double vb[3] = {0.0, 0.0, 0.0};
+          double Eb, Mb[3];
+          c2p_vjp(J, eb, vb, Eb, Mb);
+          G[cell] = G[cell] + (R)Eb;
+          for (int k = 0; k < 3; ++k) G[(1 + k) * nc + cell] = G[(1 + k) * nc + cell] + (R)Mb[k];
+        }
+        if (t == 0) {
+          double* gr = a.grad + 5 * j;
+          gr[0] += a.bdt * dJdP * jt.crcf * Tj * Tj * Tj * ell / (hc * hc);
+          gr[1] += a.bdt * dJdP * jt.crcf * Tj * Tj / hc;
+          for (int d = 0; d < 3; ++d) {
+            const double dTj = (red[6 + d][0] - Tj * red[9 + d][0]) / wsum;
+            gr[2 + d] += a.bdt * (Pj * red[3 + d][0] + dJdT * dTj);
+          }
+        }
+      }
+    }
+    __syncthreads();
+  }
+}
+
+template <class R>
+__global__ void __launch_bounds__(256) k_copy(const R* __restrict__ src, R* __restrict__ dst, long long n) {
+  const long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q < n) dst[q] = src[q];
+}
+
+__global__ void k_copy_f64(const double* __restrict__ src, double* __restrict__ dst, int n) {
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q < n) dst[q] = src[q];
+}
+
+template <class R>
+__global__ void __launch_bounds__(256) k_fill(R* dst, long long n, R v) {
+  const long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q < n) dst[q] = v;
+}
+
+// ---------------------------------------------------------------------------
+// eps2 = sum (y^2 - x^2) e / sum (y^2 + x^2) e on the z = 0 plane (mean of
+// the two middle planes for even nz).  Partial sums per block, then one block;
+// the seed kernel writes d eps2 / dU on those planes (other cells: 0).
+__device__ __forceinline__ void z0_planes(int nz, int& k0, int& k1) {
+  if (nz % 2 == 0) {
+    k0 = nz / 2 - 1;
+    k1 = nz / 2;
+  } else {
+    k0 = k1 = (nz - 1) / 2;
+  }
+}
+
+template <class R>
+__global__ void __launch_bounds__(256) k_eps2_partial(const R* __restrict__ U, Grid g, double* part) {
+  const int nx = g.n[0], ny = g.n[1];
+  int k0, k1;
+  z0_planes(g.n[2], k0, k1);
+  const long long nc = g.nc;
+  double num = 0.0, den = 0.0;
+  unsigned fix = 0;
+  for (long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x; q < (long long)nx * ny;
+       q += (long long)gridDim.x * blockDim.x) {
+    const int i = (int)(q % nx), j = (int)(q / nx);
+    const double x = cell_centre(i, nx, g.dx[0]), y = cell_centre(j, ny, g.dx[1]);
+    const long long ca = ((long long)k0 * ny + j) * nx + i, cb = ((long long)k1 * ny + j) * nx + i;
+    const PrimV pa = c2p((double)U[ca], (double)U[nc + ca], (double)U[2 * nc + ca], (double)U[3 * nc + ca], fix);
+    const PrimV pb = c2p((double)U[cb], (double)U[nc + cb], (double)U[2 * nc + cb], (double)U[3 * nc + cb], fix);
+    const double e = 0.5 * (pa.e + pb.e);
+    num += (y * y - x * x) * e;
+    den += (y * y + x * x) * e;
+  }
+  __shared__ double rn[256], rd[256];
+  rn[threadIdx.x] = num;
+  rd[threadIdx.x] = den;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if ((int)threadIdx.x < h) {
+      rn[threadIdx.x] += rn[threadIdx.x + h];
+      rd[threadIdx.x] += rd[threadIdx.x + h];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    part[2 * blockIdx.x] = rn[0];
+    part[2 * blockIdx.x + 1] = rd[0];
+  }
+}
+
+__global__ void __launch_bounds__(256) k_eps2_final(const double* part, int nb, double* out3) {
+  __shared__ double rn[256], rd[256];
+  double num = 0.0, den = 0.0;
+  for (int b = threadIdx.x; b < nb; b += blockDim.x) {
+    num += part[2 * b];
+    den += part[2 * b + 1];
+  }
+  rn[threadIdx.x] = num;
+  rd[threadIdx.x] = den;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if ((int)threadIdx.x < h) {
+      rn[threadIdx.x] += rn[threadIdx.x + h];
+      rd[threadIdx.x] += rd[threadIdx.x + h];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    out3[0] = rn[0] / rd[0];
+    out3[1] = rn[0];
+    out3[2] = rd[0];
+  }
+}
+
+template <class R>
+__global__ void __launch_bounds__(256) k_eps2_seed(const R* __restrict__ U, Grid g, const double* eps3, R* lam,
+                                                   double scale) {
+  const int nx = g.n[0], ny = g.n[1];
+  int k0, k1;
+  z0_planes(g.n[2], k0, k1);
+  const long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= (long long)nx * ny) return;
+  const long long nc = g.nc;
+  const int i = (int)(q % nx), j = (int)(q / nx);
+  const double x = cell_centre(i, nx, g.dx[0]), y = cell_centre(j, ny, g.dx[1]);
+  const double eps2 = eps3[0], den = eps3[2];
+  const double de = scale * 0.5 * ((y * y - x * x) - eps2 * (y * y + x * x)) / den;  // d eps2 / d e_plane
+  const int planes[2] = {k0, k1};
+  for (int p = 0; p < 2; ++p) {
+    const long long cell = ((long long)planes[p] * ny + j) * nx + i;
+    const PrimJ J = c2p_jac((double)U[cell], (double)U[nc + cell], (double)U[2 * nc + cell], (double)U[3 * nc + cell]);
+    const double vb[3] = {0.0, 0.0, 0.0};
+    double Eb, Mb[3];
+    c2p_vjp(J, de, vb, Eb, Mb);
+    if (k0 == k1 && p == 1) break;  // odd nz: the single plane takes both halves
+    const double f = (k0 == k1) ? 2.0 : 1.0;
+    lam[cell] = lam[cell] + (R)(f * Eb);
+    for (int k = 0; k < 3; ++k) lam[(1 + k) * nc + cell] = lam[(1 + k) * nc + cell] + (R)(f * Mb[k]);
+  }
+}
+
+// Adjoint of primitive (e, v, n) -> conserved (FP64 out [5][nc]):
+// E = (4/3 g2 - 1/3) e, M = 4/3 e g2 v, N = n g, g2 = 1/(1 - v^2).
+template <class R>
+__global__ void __launch_bounds__(256) k_prim_vjp(const double* __restrict__ prim, const R* __restrict__ lam,
+                                                  double* __restrict__ out, long long nc) {
+  const long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= nc) return;
+  const double e = prim[q], n = prim[4 * nc + q];
+  const double v[3] = {prim[nc + q], prim[2 * nc + q], prim[3 * nc + q]};
+  const double v2 = v[0] * v[0] + v[1] * v[1] + v[2] * v[2];
+  const double g2 = 1.0 / (1.0 - v2);
+  const double gm = sqrt(g2);
+  const double lE = (double)lam[q], lN = (double)lam[4 * nc + q];
+  const double lM[3] = {(double)lam[nc + q], (double)lam[2 * nc + q], (double)lam[3 * nc + q]};
+  const double lMv = lM[0] * v[0] + lM[1] * v[1] + lM[2] * v[2];
+  out[q] = lE * (4.0 * g2 - 1.0) / 3.0 + 4.0 / 3.0 * g2 * lMv;
+  for (int k = 0; k < 3; ++k) {
+    // d g2 / d v_k = 2 v_k g2^2
+    const double dg2 = 2.0 * v[k] * g2 * g2;
+    out[(1 + k) * nc + q] = lE * 4.0 / 3.0 * e * dg2 + 4.0 / 3.0 * e * (g2 * lM[k] + dg2 * lMv) + lN * n * v[k] * g2 * gm;
+  }
+  out[4 * nc + q] = lN * gm;
+}
+
+// ---------------------------------------------------------------------------
+// Host-side launchers.
+template <class R, int S>
+void launch_bound_adj(int AX, const AdjArgs<R>& a, long long nl, hipStream_t st) {
+  const unsigned nbb = (unsigned)((nl + 63) / 64);
+  if (AX == 0) hipLaunchKernelGGL((k_bound_adj<R, S, 0>), dim3(nbb), dim3(64), 0, st, a);
+  if (AX == 1) hipLaunchKernelGGL((k_bound_adj<R, S, 1>), dim3(nbb), dim3(64), 0, st, a);
+  if (AX == 2) hipLaunchKernelGGL((k_bound_adj<R, S, 2>), dim3(nbb), dim3(64), 0, st, a);
+}
+
+template <class R, int S>
+void launch_adj_axis_t(int AX, const AdjArgs<R>& a0, hipStream_t st) {
+  AdjArgs<R> a = a0;
+  a.inv_d = R(1.0 / a.g.dx[AX]);
+  const int n = a.g.n[AX];
+  const long long nl = AX == 0 ? (long long)a.g.n[1] * a.g.n[2]
+                               : (AX == 1 ? (long long)a.g.n[0] * a.g.n[2] : (long long)a.g.n[0] * a.g.n[1]);
+  const int tb = ((n + 63) / 64) * 64;
+  const size_t lds = (size_t)line_adj_lds_elems(n) * sizeof(R);
+  const unsigned nb = (unsigned)(((nl + 7) / 8) * 8);
+  // The outflow face n-1/2 adds to G: before the line kernel when that one
+  // finishes G (fused combine), after it when that one starts G (first).
+  const bool bound = a.g.bc[AX] == 0;
+  if (bound && a.stage != 0) launch_bound_adj<R, S>(AX, a, nl, st);
+  if (tb <= 256) {
+    if (AX == 0) hipLaunchKernelGGL((k_line_adj<R, S, 0, 256>), dim3(nb), dim3(tb), lds, st, a);
+    if (AX == 1) hipLaunchKernelGGL((k_line_adj<R, S, 1, 256>), dim3(nb), dim3(tb), lds, st, a);
+    if (AX == 2) hipLaunchKernelGGL((k_line_adj<R, S, 2, 256>), dim3(nb), dim3(tb), lds, st, a);
+  } else {
+    if (AX == 0) hipLaunchKernelGGL((k_line_adj<R, S, 0, 1024>), dim3(nb), dim3(tb), lds, st, a);
+    if (AX == 1) hipLaunchKernelGGL((k_line_adj<R, S, 1, 1024>), dim3(nb), dim3(tb), lds, st, a);
+    if (AX == 2) hipLaunchKernelGGL((k_line_adj<R, S, 2, 1024>), dim3(nb), dim3(tb), lds, st, a);
+  }
+  if (bound && a.stage == 0) launch_bound_adj<R, S>(AX, a, nl, st);
+}
+
+template <class R>
+hipError_t launch_adj_axis(int AX, const AdjArgs<R>& a, int scheme, hipStream_t st) {
+  if (scheme == kWenoJS)
+    launch_adj_axis_t<R, kWenoJS>(AX, a, st);
+  else if (scheme == kWenoLinear)
+    launch_adj_axis_t<R, kWenoLinear>(AX, a, st);
+  else
+    launch_adj_axis_t<R, kWenoZ>(AX, a, st);
+  return hipGetLastError();
+}
+
+template <class R>
+hipError_t launch_jet_adj(const JetAdjArgs& a, hipStream_t st) {
+  hipLaunchKernelGGL((k_jet_adj<R>), dim3(1), dim3(512), 0, st, a);
+  return hipGetLastError();
+}
+
+template <class R>
+hipError_t launch_copy(const R* src, R* dst, long long n, hipStream_t st) {
+  hipLaunchKernelGGL((k_copy<R>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, src, dst, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_copy_f64(const double* src, double* dst, int n, hipStream_t st) {
+  hipLaunchKernelGGL(k_copy_f64, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, src, dst, n);
+  return hipGetLastError();
+}
+
+template <class R>
+hipError_t launch_fill(R* dst, long long n, R v, hipStream_t st) {
+  hipLaunchKernelGGL((k_fill<R>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, dst, n, v);
+  return hipGetLastError();
+}
+
+template <class R>
+hipError_t launch_eps2(const R* U, const Grid& g, double* part, double* out3, hipStream_t st) {
+  hipLaunchKernelGGL((k_eps2_partial<R>), dim3(256), dim3(256), 0, st, U, g, part);
+  hipLaunchKernelGGL(k_eps2_final, dim3(1), dim3(256), 0, st, part, 256, out3);
+  return hipGetLastError();
+}
+
+template <class R>
+hipError_t launch_eps2_seed(const R* U, const Grid& g, const double* out3, R* lam, double scale, hipStream_t st) {
+  const long long np = (long long)g.n[0] * g.n[1];
+  hipLaunchKernelGGL((k_eps2_seed<R>), dim3((unsigned)((np + 255) / 256)), dim3(256), 0, st, U, g, out3, lam, scale);
+  return hipGetLastError();
+}
+
+template <class R>
+hipError_t launch_prim_vjp(const double* prim, const R* lam, double* out, long long nc, hipStream_t st) {
+  hipLaunchKernelGGL((k_prim_vjp<R>), dim3((unsigned)((nc + 255) / 256)), dim3(256), 0, st, prim, lam, out, nc);
+  return hipGetLastError();
+}
+
+#define HYDRO_ADJ_INSTANTIATE(R)                                                                               \
+  template hipError_t launch_adj_axis<R>(int, const AdjArgs<R>&, int, hipStream_t);                           \
+  template hipError_t launch_jet_adj<R>(const JetAdjArgs&, hipStream_t);                                     \
+  template hipError_t launch_copy<R>(const R*, R*, long long, hipStream_t);                                   \
+  template hipError_t launch_fill<R>(R*, long long, R, hipStream_t);                                          \
+  template hipError_t launch_eps2<R>(const R*, const Grid&, double*, double*, hipStream_t);                    \
+  template hipError_t launch_eps2_seed<R>(const R*, const Grid&, const double*, R*, double, hipStream_t);       \
+  template hipError_t launch_prim_vjp<R>(const double*, const R*, double*, long long, hipStream_t);
+
+HYDRO_ADJ_INSTANTIATE(double)
+HYDRO_ADJ_INSTANTIATE(float)
+
+}  // namespace hydro

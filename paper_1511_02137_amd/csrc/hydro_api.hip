@@ -29,6 +29,21 @@ hipError_t launch_prim_to_cons(const double* prim, R* U, long long nc, hipStream
 template <class R>
 hipError_t launch_primitives(const R* U, R* prim, long long nc, double g, double hc, unsigned long long* fixups,
                              hipStream_t st);
+template <class R>
+hipError_t launch_adj_axis(int AX, const AdjArgs<R>& a, int scheme, hipStream_t st);
+template <class R>
+hipError_t launch_jet_adj(const JetAdjArgs& a, hipStream_t st);
+template <class R>
+hipError_t launch_copy(const R* src, R* dst, long long n, hipStream_t st);
+hipError_t launch_copy_f64(const double* src, double* dst, int n, hipStream_t st);
+template <class R>
+hipError_t launch_fill(R* dst, long long n, R v, hipStream_t st);
+template <class R>
+hipError_t launch_eps2(const R* U, const Grid& g, double* part, double* out3, hipStream_t st);
+template <class R>
+hipError_t launch_eps2_seed(const R* U, const Grid& g, const double* out3, R* lam, double scale, hipStream_t st);
+template <class R>
+hipError_t launch_prim_vjp(const double* prim, const R* lam, double* out, long long nc, hipStream_t st);
 }  // namespace hydro
 
 using namespace hydro;
@@ -45,6 +60,18 @@ struct hydro_ctx {
   void* U2 = nullptr;
   void* D = nullptr;
   double* part = nullptr;
+  double* eps_part = nullptr;  // 256 x 2 partial sums of eps2
+  double* eps_out = nullptr;   // eps2, numerator, denominator
+  // adjoint region (capacity adj_k steps)
+  int adj_k = 0;
+  unsigned char* states = nullptr;  // 3 adj_k stage states
+  void* lamA = nullptr;
+  void* lamB = nullptr;
+  void* lacc = nullptr;
+  void* G = nullptr;
+  double* Ehist = nullptr;  // [adj_k][kMaxJets]
+  double* Esave = nullptr;  // [kMaxJets + 1]
+  size_t field_bytes = 0;
   int64_t step = 0;
   int seg = 32;      // march segment length
   int yz_tile = 1;   // 1: y/z faces from LDS tiles, 0: register-window marches
@@ -96,18 +123,34 @@ bool config_ok(const hydro_config* c, std::string* why) {
 }
 
 struct WsLayout {
-  size_t U1, U2, D, part, total;
+  size_t U1, U2, D, part, eps_part, eps_out, fwd_total;
+  size_t states, lamA, lamB, lacc, G, Ehist, Esave, total;
+  size_t field;
 };
 
 WsLayout layout(const hydro_config* c, int adjoint_k) {
-  (void)adjoint_k;
   WsLayout L;
   const size_t field = align256((size_t)5 * ncells(c) * elem_size(c));
+  L.field = field;
   L.U1 = 0;
   L.U2 = L.U1 + field;
   L.D = L.U2 + field;
   L.part = L.D + field;
-  L.total = L.part + align256((size_t)kSumBlocks * 5 * sizeof(double));
+  L.eps_part = L.part + align256((size_t)kSumBlocks * 5 * sizeof(double));
+  L.eps_out = L.eps_part + align256(512 * sizeof(double));
+  L.fwd_total = L.eps_out + align256(8 * sizeof(double));
+  L.states = L.lamA = L.lamB = L.lacc = L.G = L.Ehist = L.Esave = L.fwd_total;
+  L.total = L.fwd_total;
+  if (adjoint_k > 0) {
+    L.states = L.fwd_total;
+    L.lamA = L.states + (size_t)3 * adjoint_k * field;
+    L.lamB = L.lamA + field;
+    L.lacc = L.lamB + field;
+    L.G = L.lacc + field;
+    L.Ehist = L.G + field;
+    L.Esave = L.Ehist + align256((size_t)adjoint_k * kMaxJets * sizeof(double));
+    L.total = L.Esave + align256((kMaxJets + 1) * sizeof(double));
+  }
   return L;
 }
 
@@ -258,6 +301,103 @@ int step_impl(hydro_ctx* ctx, R* U, int nsteps, hipStream_t st) {
   return HYDRO_OK;
 }
 
+bool adjoint_fits(const hydro_config* c, std::string* why) {
+  for (int d = 0; d < 3; ++d) {
+    const size_t lds = (size_t)line_adj_lds_elems(c->n[d]) * elem_size(c);
+    if (lds > 65536 || c->n[d] > 1024) {
+      if (why) *why = "grid too large along an axis for the line adjoint (LDS line tile)";
+      return false;
+    }
+  }
+  return true;
+}
+
+template <class R>
+int adjoint_impl(hydro_ctx* ctx, const R* Uc, int64_t step0, const double* E0, int K, R* lam, double* grad,
+                 hipStream_t st) {
+  const hydro_config& c = ctx->cfg;
+  const double dt = c.dt;
+  const long long n5 = 5 * ctx->g.nc;
+  const size_t fe = ctx->field_bytes / sizeof(R);  // elements per state block
+  R* S = reinterpret_cast<R*>(ctx->states);
+  auto st_ptr = [&](int i, int k) { return S + (size_t)(3 * i + k) * fe; };
+  R* lamA = static_cast<R*>(ctx->lamA);
+  R* lamB = static_cast<R*>(ctx->lamB);
+  R* acc = static_cast<R*>(ctx->lacc);
+  R* G = static_cast<R*>(ctx->G);
+  hipError_t e = hipSuccess;
+#define HYDRO_TRY(x)                        \
+  do {                                      \
+    e = (x);                                \
+    if (e != hipSuccess) return hip_fail(ctx, e, #x); \
+  } while (0)
+  // keep the context's jet energies and ledger
+  HYDRO_TRY(launch_copy_f64(ctx->dev->E_jet, ctx->Esave, kMaxJets, st));
+  HYDRO_TRY(launch_copy_f64(&ctx->dev->ledger, ctx->Esave + kMaxJets, 1, st));
+  // the checkpoint's jet energies (host memory): ordered after the saves above
+  HYDRO_TRY(hipStreamSynchronize(st));
+  if (ctx->njet > 0) HYDRO_TRY(hipMemcpy(ctx->dev->E_jet, E0, (size_t)ctx->njet * sizeof(double), hipMemcpyHostToDevice));
+  // recompute the stage states of the segment
+  HYDRO_TRY(launch_copy<R>(Uc, st_ptr(0, 0), n5, st));
+  for (int i = 0; i < K; ++i) {
+    const double tn = c.t0 + (double)(step0 + i) * dt;
+    HYDRO_TRY(launch_copy_f64(ctx->dev->E_jet, ctx->Ehist + (size_t)i * kMaxJets, kMaxJets, st));
+    HYDRO_TRY(stage_impl<R>(ctx, st_ptr(i, 0), st_ptr(i, 0), st_ptr(i, 1), 1, tn, st));
+    HYDRO_TRY(stage_impl<R>(ctx, st_ptr(i, 1), st_ptr(i, 0), st_ptr(i, 2), 2, tn + dt, st));
+    R* out = (i + 1 < K) ? st_ptr(i + 1, 0) : static_cast<R*>(ctx->U1);
+    HYDRO_TRY(stage_impl<R>(ctx, st_ptr(i, 2), st_ptr(i, 0), out, 3, tn + 0.5 * dt, st));
+  }
+  // reverse sweep
+  AdjArgs<R> a;
+  a.g = ctx->g;
+  a.eps = (R)c.weno_eps;
+  a.fixups = &ctx->dev->fixups;
+  a.G = G;
+  a.dt = (R)dt;
+  a.acc = acc;
+  a.stage = 0;
+  const double cst[3] = {0.0, 1.0, 0.5};
+  const double bst[3] = {1.0, 0.25, 2.0 / 3.0};
+  for (int i = K - 1; i >= 0; --i) {
+    const double tn = c.t0 + (double)(step0 + i) * dt;
+    for (int k = 3; k >= 1; --k) {
+      const R* lY = (k == 3) ? lam : (k == 2 ? lamA : lamB);
+      a.lW = (k == 3) ? lamA : (k == 2 ? lamB : lam);
+      a.W = st_ptr(i, k - 1);
+      a.mu = lY;
+      // x starts G, y adds, the jet source adds at its cells, z adds and
+      // applies the reverse RK combine (lW, acc)
+      for (int ax = 0; ax < 3; ++ax) {
+        if (ax == 2 && ctx->njet > 0) {
+          JetAdjArgs j;
+          j.W = a.W;
+          j.mu = lY;
+          j.G = G;
+          j.s = ctx->dev;
+          j.Ehist = ctx->Ehist + (size_t)i * kMaxJets;
+          j.grad = grad;
+          j.g = ctx->g;
+          j.njet = ctx->njet;
+          j.deposit = c.deposit;
+          j.t = tn + cst[k - 1] * dt;
+          j.bdt = bst[k - 1] * dt;
+          j.eos_dof = c.eos_dof;
+          j.hbarc = c.hbarc;
+          HYDRO_TRY(launch_jet_adj<R>(j, st));
+        }
+        a.first = ax == 0 ? 1 : 0;
+        a.stage = ax == 2 ? k : 0;
+        ProfScope p(ctx, HYDRO_K_ADJ, st);
+        HYDRO_TRY(launch_adj_axis<R>(ax, a, c.weno, st));
+      }
+    }
+  }
+  HYDRO_TRY(launch_copy_f64(ctx->Esave, ctx->dev->E_jet, kMaxJets, st));
+  HYDRO_TRY(launch_copy_f64(ctx->Esave + kMaxJets, &ctx->dev->ledger, 1, st));
+#undef HYDRO_TRY
+  return HYDRO_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -284,6 +424,7 @@ void hydro_default_config(hydro_config* c) {
 
 size_t hydro_workspace_bytes(const hydro_config* cfg, int adjoint_k) {
   if (!config_ok(cfg, nullptr) || adjoint_k < 0) return 0;
+  if (adjoint_k > 0 && !adjoint_fits(cfg, nullptr)) return 0;
   return layout(cfg, adjoint_k).total;
 }
 
@@ -325,6 +466,24 @@ int hydro_init(const hydro_config* cfg, const double* prim0, void* U, void* work
   ctx->U2 = ctx->ws + L.U2;
   ctx->D = ctx->ws + L.D;
   ctx->part = reinterpret_cast<double*>(ctx->ws + L.part);
+  ctx->eps_part = reinterpret_cast<double*>(ctx->ws + L.eps_part);
+  ctx->eps_out = reinterpret_cast<double*>(ctx->ws + L.eps_out);
+  ctx->field_bytes = L.field;
+  {
+    int k = 0;
+    while (k < 100000 && layout(cfg, k + 1).total <= ws_bytes) ++k;
+    ctx->adj_k = k;
+    if (k > 0) {
+      const WsLayout A = layout(cfg, k);
+      ctx->states = ctx->ws + A.states;
+      ctx->lamA = ctx->ws + A.lamA;
+      ctx->lamB = ctx->ws + A.lamB;
+      ctx->lacc = ctx->ws + A.lacc;
+      ctx->G = ctx->ws + A.G;
+      ctx->Ehist = reinterpret_cast<double*>(ctx->ws + A.Ehist);
+      ctx->Esave = reinterpret_cast<double*>(ctx->ws + A.Esave);
+    }
+  }
   // march segment: full short axes, 32 cells otherwise
   ctx->seg = 32;
   hipStream_t st = static_cast<hipStream_t>(stream);
@@ -493,6 +652,93 @@ int hydro_diag(hydro_ctx* ctx, int64_t* fixups) {
   if (e == hipSuccess) e = hipMemcpy(&f, &ctx->dev->fixups, sizeof(f), hipMemcpyDeviceToHost);
   if (e != hipSuccess) return hip_fail(ctx, e, "hydro_diag");
   *fixups = (int64_t)f;
+  return HYDRO_OK;
+}
+
+int hydro_reset(hydro_ctx* ctx, const double* prim0, void* U, void* stream) {
+  if (!ctx || !prim0 || !U) return fail(ctx, HYDRO_EINVAL, "bad arguments to hydro_reset");
+  if (!is_device_pointer(prim0)) return fail(ctx, HYDRO_EINVAL, "hydro_reset needs prim0 in device memory");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  hipError_t e = ctx->cfg.precision == HYDRO_F32
+                     ? launch_prim_to_cons<float>(prim0, static_cast<float*>(U), ctx->g.nc, st)
+                     : launch_prim_to_cons<double>(prim0, static_cast<double*>(U), ctx->g.nc, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  double E0[kMaxJets];
+  for (int j = 0; j < ctx->njet; ++j) E0[j] = ctx->jets[j].E0;
+  const double zero = 0.0;
+  if (e == hipSuccess && ctx->njet > 0)
+    e = hipMemcpy(ctx->dev->E_jet, E0, (size_t)ctx->njet * sizeof(double), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(&ctx->dev->ledger, &zero, sizeof(double), hipMemcpyHostToDevice);
+  if (e != hipSuccess) return hip_fail(ctx, e, "hydro_reset");
+  ctx->step = 0;
+  return HYDRO_OK;
+}
+
+int hydro_set_jet(hydro_ctx* ctx, int id, const hydro_jet* jet) {
+  if (!ctx || !jet || id < 0 || id >= ctx->njet) return fail(ctx, HYDRO_EINVAL, "bad arguments to hydro_set_jet");
+  double n2 = jet->dir[0] * jet->dir[0] + jet->dir[1] * jet->dir[1] + jet->dir[2] * jet->dir[2];
+  if (!(std::fabs(n2 - 1.0) < 1e-9)) return fail(ctx, HYDRO_EINVAL, "jet direction must be a unit vector");
+  JetDev jd;
+  for (int d = 0; d < 3; ++d) {
+    jd.x0[d] = jet->x0[d];
+    jd.dir[d] = jet->dir[d];
+  }
+  jd.t_start = jet->t_start;
+  jd.kappa_rad = jet->kappa_rad;
+  jd.kappa_coll = jet->kappa_coll;
+  jd.crcf = jet->cr_over_cf;
+  hipError_t e = hipDeviceSynchronize();
+  if (e == hipSuccess) e = hipMemcpy(&ctx->dev->jets[id], &jd, sizeof(jd), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(&ctx->dev->E_jet[id], &jet->E0, sizeof(double), hipMemcpyHostToDevice);
+  if (e != hipSuccess) return hip_fail(ctx, e, "hydro_set_jet");
+  ctx->jets[id] = *jet;
+  return HYDRO_OK;
+}
+
+int hydro_loss_eps2(hydro_ctx* ctx, const void* U, double* eps2_out, void* seed, double scale, void* stream) {
+  if (!ctx || !U) return fail(ctx, HYDRO_EINVAL, "bad arguments to hydro_loss_eps2");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const long long n5 = 5 * ctx->g.nc;
+  hipError_t e;
+  if (ctx->cfg.precision == HYDRO_F32) {
+    e = launch_eps2<float>(static_cast<const float*>(U), ctx->g, ctx->eps_part, ctx->eps_out, st);
+    if (e == hipSuccess && seed) e = launch_fill<float>(static_cast<float*>(seed), n5, 0.0f, st);
+    if (e == hipSuccess && seed)
+      e = launch_eps2_seed<float>(static_cast<const float*>(U), ctx->g, ctx->eps_out, static_cast<float*>(seed), scale, st);
+  } else {
+    e = launch_eps2<double>(static_cast<const double*>(U), ctx->g, ctx->eps_part, ctx->eps_out, st);
+    if (e == hipSuccess && seed) e = launch_fill<double>(static_cast<double*>(seed), n5, 0.0, st);
+    if (e == hipSuccess && seed)
+      e = launch_eps2_seed<double>(static_cast<const double*>(U), ctx->g, ctx->eps_out, static_cast<double*>(seed), scale, st);
+  }
+  if (e == hipSuccess && eps2_out) e = launch_copy_f64(ctx->eps_out, eps2_out, 1, st);
+  if (e != hipSuccess) return hip_fail(ctx, e, "hydro_loss_eps2");
+  return HYDRO_OK;
+}
+
+int hydro_adjoint_step(hydro_ctx* ctx, const void* U_ckpt, int64_t step0, const double* E_jet0, int nsteps,
+                       void* lambda, double* grad_jets, void* stream) {
+  if (!ctx || !U_ckpt || !lambda || nsteps < 0 || step0 < 0) return fail(ctx, HYDRO_EINVAL, "bad arguments to hydro_adjoint_step");
+  if (ctx->njet > 0 && (!E_jet0 || !grad_jets)) return fail(ctx, HYDRO_EINVAL, "jets need E_jet0 and grad_jets");
+  if (nsteps > ctx->adj_k) return fail(ctx, HYDRO_EINVAL, "workspace holds fewer adjoint steps than nsteps");
+  std::string why;
+  if (!adjoint_fits(&ctx->cfg, &why)) return fail(ctx, HYDRO_EINVAL, why);
+  if (nsteps == 0) return HYDRO_OK;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  if (ctx->cfg.precision == HYDRO_F32)
+    return adjoint_impl<float>(ctx, static_cast<const float*>(U_ckpt), step0, E_jet0, nsteps, static_cast<float*>(lambda),
+                               grad_jets, st);
+  return adjoint_impl<double>(ctx, static_cast<const double*>(U_ckpt), step0, E_jet0, nsteps,
+                              static_cast<double*>(lambda), grad_jets, st);
+}
+
+int hydro_init_vjp(hydro_ctx* ctx, const double* prim0, const void* lambda, double* grad_prim, void* stream) {
+  if (!ctx || !prim0 || !lambda || !grad_prim) return fail(ctx, HYDRO_EINVAL, "bad arguments to hydro_init_vjp");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  hipError_t e = ctx->cfg.precision == HYDRO_F32
+                     ? launch_prim_vjp<float>(prim0, static_cast<const float*>(lambda), grad_prim, ctx->g.nc, st)
+                     : launch_prim_vjp<double>(prim0, static_cast<const double*>(lambda), grad_prim, ctx->g.nc, st);
+  if (e != hipSuccess) return hip_fail(ctx, e, "hydro_init_vjp");
   return HYDRO_OK;
 }
 

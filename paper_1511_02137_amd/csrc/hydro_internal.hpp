@@ -71,4 +71,45 @@ struct JetArgs {
   double eos_dof, hbarc;
 };
 
+// Arguments of the line adjoint kernels (device pointers).
+template <class R>
+struct AdjArgs {
+  const R* W;   // stage input
+  const R* mu;  // adjoint of the stage output (lambda_Y)
+  R* G;         // (dL/dW)^T mu accumulator [5][nc]
+  Grid g;
+  R inv_d;      // 1/dx of the kernel's axis (set by the launcher)
+  R eps;        // epsilon of the WENO weights
+  int first;    // 1: G = contribution, 0: G += contribution
+  unsigned long long* fixups;
+  // RK combine in reverse, fused into the last axis (stage 0: none, G is
+  // stored).  With b_k the stage weight of W and a_k that of U^n:
+  //   lW = b_k (mu + dt G), acc (adjoint of U^n) += a_k mu; stage 1: lW = acc + mu + dt G.
+  int stage;
+  R dt;
+  R* acc;
+  R* lW;
+};
+
+// LDS of the line adjoint kernel, in elements of the field type: split fluxes
+// [2][5][n+8] and the face partials of both splits [2][7][n+16] (face x at
+// x+8, zero pads so the gather needs no bounds tests).
+constexpr long long line_adj_lds_elems(int n) { return 10LL * (n + 8) + 14LL * (n + 16); }
+
+// Arguments of the jet-source adjoint kernel.
+struct JetAdjArgs {
+  const void* W;        // stage input
+  const void* mu;       // adjoint of the stage output
+  void* G;              // accumulator
+  DevScalars* s;
+  const double* Ehist;  // jet energies at the start of the step [kMaxJets]
+  double* grad;         // parameter gradients [njet][5] (+=)
+  Grid g;
+  int njet;
+  int deposit;
+  double t;             // stage time
+  double bdt;           // b_k * dt of the stage
+  double eos_dof, hbarc;
+};
+
 }  // namespace hydro

@@ -24,203 +24,10 @@
 
 #include <hip/hip_runtime.h>
 
+#include "hydro_device.hpp"
 #include "hydro_internal.hpp"
 
 namespace hydro {
-
-// ---------------------------------------------------------------------------
-// Ghost-cell index map: outflow = copy of the edge cell, periodic = wrap.
-__device__ __forceinline__ int map_idx(int p, int n, int bc) {
-  if (bc) {
-    int r = p % n;
-    return r < 0 ? r + n : r;
-  }
-  return min(max(p, 0), n - 1);
-}
-
-template <class R>
-__device__ __forceinline__ void load5(const R* __restrict__ W, long long nc, long long cell, R u[5]) {
-#pragma unroll
-  for (int c = 0; c < 5; ++c) u[c] = W[c * nc + cell];
-}
-
-// ---------------------------------------------------------------------------
-// Conserved -> primitive for p = e/3 (FP64): e = 3(E^2 - M^2)/(E + sqrt(4E^2
-// - 3M^2)), v = M/(E + e/3).  Non-admissible cells are fixed up for the
-// primitive calculation only (E <= 1e-12: vacuum at rest; |M| >= (1-1e-10) E:
-// M rescaled to that speed) and counted.
-struct PrimV {
-  double e;
-  double v[3];
-};
-
-__device__ __forceinline__ PrimV c2p(double E, double Mx, double My, double Mz, unsigned& fix) {
-  PrimV r;
-  if (E <= kEFloor) {
-    ++fix;
-    r.e = kEFloor;
-    r.v[0] = r.v[1] = r.v[2] = 0.0;
-    return r;
-  }
-  double M2 = Mx * Mx + My * My + Mz * Mz;
-  if (M2 >= kVCap * kVCap * E * E) {
-    ++fix;
-    const double sc = kVCap * E / sqrt(M2);
-    Mx = Mx * sc;
-    My = My * sc;
-    Mz = Mz * sc;
-    M2 = Mx * Mx + My * My + Mz * Mz;
-  }
-  const double e = 3.0 * (E * E - M2) / (E + sqrt(4.0 * E * E - 3.0 * M2));
-  const double W = E + e / 3.0;
-  r.e = e;
-  r.v[0] = Mx / W;
-  r.v[1] = My / W;
-  r.v[2] = Mz / W;
-  return r;
-}
-
-template <class R>
-__device__ __forceinline__ PrimV c2p(const R u[5], unsigned& fix) {
-  return c2p((double)u[0], (double)u[1], (double)u[2], (double)u[3], fix);
-}
-
-// Physical flux along axis AX and its Lax-Friedrichs split (alpha = 1):
-// f = (M_AX, M_x v_AX + p d_{x,AX}, M_y v_AX + p d_{y,AX}, M_z v_AX + p d_{z,AX}, N v_AX).
-template <class R, int AX>
-__device__ __forceinline__ void split_flux(const R u[5], const PrimV& p, R Fp[5], R Fm[5]) {
-  const R vd = (R)p.v[AX];
-  const R pr = (R)(p.e / 3.0);
-  R f[5];
-  f[0] = u[1 + AX];
-  f[1] = (AX == 0) ? u[1] * vd + pr : u[1] * vd;
-  f[2] = (AX == 1) ? u[2] * vd + pr : u[2] * vd;
-  f[3] = (AX == 2) ? u[3] * vd + pr : u[3] * vd;
-  f[4] = u[4] * vd;
-#pragma unroll
-  for (int c = 0; c < 5; ++c) {
-    Fp[c] = R(0.5) * (f[c] + u[c]);
-    Fm[c] = R(0.5) * (f[c] - u[c]);
-  }
-}
-
-// ---------------------------------------------------------------------------
-// WENO7 value at x_{i+1/2} from the left, a0..a6 = a_{i-3}..a_{i+3}.
-// The candidates q_k of the 4-point stencils enter as d_k (q_k - a_{i}),
-// d = (1, 12, 18, 4)/35, written with the first differences, and the result
-// is a_i + sum w_k d_k (q_k - a_i) / sum w_k d_k.  Smoothness indicators (Jiang-Shu: the
-// integral over cell i of the squared derivatives of stencil k's cubic) are
-// evaluated from the nested differences D1, D2, D3 of the stencil values:
-//   b_k = s_k^2 + 13/12 c_k^2 + 781/720 D3_k^2 + eps,
-//   s_k = D1_k + h_k D2_k + m_k D3_k   (h = 5/2, 3/2, 1/2, -1/2;
-//                                        m = 11/6, 1/3, -1/6, 1/3),
-//   c_k = D2_k + g_k D3_k             (g = 2, 1, 0, -1),
-// so they vanish exactly on flat stencils.  WENO-Z (p = 2):
-// w_k = 1 + (tau/b_k)^2, tau = |b0 - b3 + 3(b1 - b2)|; Jiang-Shu: w_k = 1/b_k^2;
-// the result is sum w_k d_k q_k / sum w_k d_k.
-template <class R>
-__device__ __forceinline__ R rcp_approx(R x);
-template <>
-__device__ __forceinline__ float rcp_approx<float>(float x) {
-  return __builtin_amdgcn_rcpf(x);
-}
-template <>
-__device__ __forceinline__ double rcp_approx<double>(double x) {
-  return 1.0 / x;
-}
-
-template <class R>
-__device__ __forceinline__ R smoothness(R D1, R D2, R D3, R h, R m, R g, R eps) {
-  const R sk = fma(m, D3, fma(h, D2, D1));
-  const R ck = fma(g, D3, D2);
-  return fma(sk, sk, fma(R(13.0 / 12.0) * ck, ck, fma(R(781.0 / 720.0) * D3, D3, eps)));
-}
-
-// Reciprocal for FP64: hardware estimate, two Newton steps (quadratic
-// convergence from the estimate's ~23 bits to full precision).
-__device__ __forceinline__ double rcp_nr(double x) {
-  double r = __builtin_amdgcn_rcp(x);
-  r = fma(fma(-x, r, 1.0), r, r);
-  r = fma(fma(-x, r, 1.0), r, r);
-  return r;
-}
-
-// num / den from one reciprocal plus a residual correction.
-__device__ __forceinline__ double div_nr(double num, double den) {
-  const double r = rcp_nr(den);
-  const double q = num * r;
-  return fma(fma(-den, q, num), r, q);
-}
-
-template <class R, int S>
-__device__ __forceinline__ R weno7(R a0, R a1, R a2, R a3, R a4, R a5, R a6, R eps) {
-  // nested differences of the seven values
-  const R e0 = a1 - a0, e1 = a2 - a1, e2 = a3 - a2, e3 = a4 - a3, e4 = a5 - a4, e5 = a6 - a5;
-  // candidates as d_k (q_k - a3), from the differences
-  const R r0 = fma(R(13.0 / 420.0), e2, fma(R(-10.0 / 420.0), e1, R(3.0 / 420.0) * e0));
-  const R r1 = fma(R(3.0 / 35.0), e3, fma(R(4.0 / 35.0), e2, R(-1.0 / 35.0) * e1));
-  const R r2 = fma(R(-3.0 / 70.0), e4, fma(R(18.0 / 70.0), e3, R(3.0 / 70.0) * e2));
-  const R r3 = fma(R(1.0 / 105.0), e5, fma(R(-4.0 / 105.0), e4, R(9.0 / 105.0) * e3));
-  if (S == kWenoLinear) return a3 + ((r0 + r1) + (r2 + r3));
-
-  const R f0 = e1 - e0, f1 = e2 - e1, f2 = e3 - e2, f3 = e4 - e3, f4 = e5 - e4;
-  const R g0 = f1 - f0, g1 = f2 - f1, g2 = f3 - f2, g3 = f4 - f3;
-  const R b0 = smoothness<R>(e0, f0, g0, R(2.5), R(11.0 / 6.0), R(2), eps);
-  const R b1 = smoothness<R>(e1, f1, g1, R(1.5), R(1.0 / 3.0), R(1), eps);
-  const R b2 = smoothness<R>(e2, f2, g2, R(0.5), R(-1.0 / 6.0), R(0), eps);
-  const R b3 = smoothness<R>(e3, f3, g3, R(-0.5), R(1.0 / 3.0), R(-1), eps);
-
-  if (sizeof(R) == 8) {
-    // Weights over a common denominator: with B_k = b_k^2 the WENO-Z weight
-    // d_k (1 + tau^2/B_k) is proportional to d_k (B_k + tau^2) prod_{j!=k} B_j,
-    // the Jiang-Shu weight d_k/B_k to d_k prod_{j!=k} B_j.  One division.
-    const R B0 = b0 * b0, B1 = b1 * b1, B2 = b2 * b2, B3 = b3 * b3;
-    const R P01 = B0 * B1, P23 = B2 * B3;
-    R A0 = B1 * P23, A1 = B0 * P23, A2 = P01 * B3, A3 = P01 * B2;
-    if (S == kWenoZ) {
-      const R tau = fabs(fma(R(3), b1 - b2, b0 - b3));
-      const R t2 = tau * tau;
-      A0 = (B0 + t2) * A0;
-      A1 = (B1 + t2) * A1;
-      A2 = (B2 + t2) * A2;
-      A3 = (B3 + t2) * A3;
-    }
-    const R num = fma(A3, r3, fma(A2, r2, fma(A1, r1, A0 * r0)));
-    const R den = fma(A3, R(4.0 / 35.0), fma(A2, R(18.0 / 35.0), fma(A1, R(12.0 / 35.0), A0 * R(1.0 / 35.0))));
-    return a3 + (R)div_nr((double)num, (double)den);
-  } else {
-    const R i0 = rcp_approx<R>(b0), i1 = rcp_approx<R>(b1), i2 = rcp_approx<R>(b2), i3 = rcp_approx<R>(b3);
-    R w0, w1, w2, w3;
-    if (S == kWenoZ) {
-      const R tau = fabs(fma(R(3), b1 - b2, b0 - b3));
-      const R s0 = tau * i0, s1 = tau * i1, s2 = tau * i2, s3 = tau * i3;
-      w0 = fma(s0, s0, R(1));
-      w1 = fma(s1, s1, R(1));
-      w2 = fma(s2, s2, R(1));
-      w3 = fma(s3, s3, R(1));
-    } else {
-      w0 = i0 * i0;
-      w1 = i1 * i1;
-      w2 = i2 * i2;
-      w3 = i3 * i3;
-    }
-    const R num = fma(w3, r3, fma(w2, r2, fma(w1, r1, w0 * r0)));
-    const R den = fma(w3, R(4.0 / 35.0), fma(w2, R(18.0 / 35.0), fma(w1, R(12.0 / 35.0), w0 * R(1.0 / 35.0))));
-    return fma(num, rcp_approx<R>(den), a3);
-  }
-}
-
-// Face flux from the 8-point window Fp/Fm[m] = split fluxes at i-3+m:
-// F(i+1/2) = R_L(F+_{i-3..i+3}) + R_L(F-_{i+4..i-2}).
-template <class R, int S>
-__device__ __forceinline__ R face_flux(const R* fp, const R* fm, R eps) {
-  return weno7<R, S>(fp[0], fp[1], fp[2], fp[3], fp[4], fp[5], fp[6], eps) +
-         weno7<R, S>(fm[7], fm[6], fm[5], fm[4], fm[3], fm[2], fm[1], eps);
-}
-
-__device__ __forceinline__ void add_fixups(unsigned long long* ctr, unsigned fix) {
-  if (fix) atomicAdd(ctr, (unsigned long long)fix);
-}
 
 // ---------------------------------------------------------------------------
 // x-faces: one workgroup per row (blockDim = nx rounded up to 64).
@@ -546,24 +353,6 @@ __global__ void __launch_bounds__(512) k_tile(StageArgs<R> a) {
 
 // ---------------------------------------------------------------------------
 // Jet source (Eq. 2 and 3).  One workgroup of 512 threads; jets in order.
-__device__ __forceinline__ int ngp_index(double x, int n, double dx) {
-  const double x_lo = -0.5 * n * dx;
-  const double u = (x - x_lo) / dx + 1e-9;
-  const double f = floor(u);
-  if (f < 0.0 || f >= (double)n) return -1;
-  return (int)f;
-}
-
-__device__ __forceinline__ double temperature(double e, double g, double hc) {
-  return pow(30.0 * e * (hc * hc * hc) / (g * 3.14159265358979323846 * 3.14159265358979323846), 0.25);
-}
-
-__device__ __forceinline__ double energy_loss(const JetDev& jt, double T, double ell, double hc) {
-  return jt.kappa_coll * jt.crcf * T * T / hc + jt.kappa_rad * jt.crcf * T * T * T * ell / (hc * hc);
-}
-
-__device__ __forceinline__ double cell_centre(int i, int n, double dx) { return (i - 0.5 * (n - 1)) * dx; }
-
 template <class R>
 __global__ void __launch_bounds__(512) k_jet(JetArgs a) {
   const R* W = static_cast<const R*>(a.W);

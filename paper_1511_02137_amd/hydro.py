@@ -25,10 +25,11 @@ EXPORTED = [
     "hydro_default_config", "hydro_workspace_bytes", "hydro_init", "hydro_add_jet", "hydro_rk3_step",
     "hydro_primitives", "hydro_rhs", "hydro_sums", "hydro_get_state", "hydro_set_state", "hydro_diag",
     "hydro_last_error", "hydro_destroy", "hydro_profile", "hydro_profile_read", "hydro_set_option",
-    "hydro_get_option",
+    "hydro_get_option", "hydro_reset", "hydro_set_jet", "hydro_loss_eps2", "hydro_adjoint_step",
+    "hydro_init_vjp",
 ]
 OPT_YZ_KERNEL, OPT_MARCH_SEG = 0, 1
-KERNELS = ["xface", "xbound", "ymarch", "jet", "zmarch", "sums"]
+KERNELS = ["xface", "xbound", "ymarch", "jet", "zmarch", "sums", "adjoint"]
 
 
 class HydroError(RuntimeError):
@@ -98,11 +99,17 @@ def load_library(path: str = LIB_PATH):
     lib.hydro_destroy.restype = None
     lib.hydro_profile.argtypes = [vp, ctypes.c_int]
     lib.hydro_set_option.argtypes = [vp, ctypes.c_int, ctypes.c_int]
+    lib.hydro_reset.argtypes = [vp, vp, vp, vp]
+    lib.hydro_set_jet.argtypes = [vp, ctypes.c_int, ctypes.POINTER(JetC)]
+    lib.hydro_loss_eps2.argtypes = [vp, vp, vp, vp, ctypes.c_double, vp]
+    lib.hydro_adjoint_step.argtypes = [vp, vp, ctypes.c_int64, dp, ctypes.c_int, vp, vp, vp]
+    lib.hydro_init_vjp.argtypes = [vp, vp, vp, vp, vp]
     lib.hydro_get_option.argtypes = [vp, ctypes.c_int, ctypes.POINTER(ctypes.c_int)]
     lib.hydro_profile_read.argtypes = [vp, dp, ctypes.POINTER(ctypes.c_int64), ctypes.c_int]
     for name in ("hydro_init", "hydro_add_jet", "hydro_rk3_step", "hydro_primitives", "hydro_rhs", "hydro_sums",
                  "hydro_get_state", "hydro_set_state", "hydro_diag", "hydro_profile", "hydro_profile_read",
-                 "hydro_set_option", "hydro_get_option"):
+                 "hydro_set_option", "hydro_get_option", "hydro_reset", "hydro_set_jet", "hydro_loss_eps2",
+                 "hydro_adjoint_step", "hydro_init_vjp"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -184,6 +191,57 @@ class Hydro:
     def _check(self, rc):
         if rc != HYDRO_OK:
             raise HydroError(rc, self.lib.hydro_last_error(self.ctx).decode())
+
+    @staticmethod
+    def _jet(x0, dir, E0, t_start, kappa_rad, kappa_coll, cr_over_cf) -> JetC:
+        j = JetC()
+        for d in range(3):
+            j.x0[d] = float(x0[d])
+            j.dir[d] = float(dir[d])
+        j.E0, j.t_start = float(E0), float(t_start)
+        j.kappa_rad, j.kappa_coll, j.cr_over_cf = float(kappa_rad), float(kappa_coll), float(cr_over_cf)
+        return j
+
+    def set_jet(self, jid: int, x0, dir=(1.0, 0.0, 0.0), E0=50.0, t_start=1.0, kappa_rad=4.0, kappa_coll=2.5,
+                cr_over_cf=1.0):
+        j = self._jet(x0, dir, E0, t_start, kappa_rad, kappa_coll, cr_over_cf)
+        self._check(self.lib.hydro_set_jet(self.ctx, int(jid), ctypes.byref(j)))
+
+    def reset(self, prim0, stream=None):
+        """U from device FP64 primitives (5, nz, ny, nx); step 0, jet energies E0, ledger 0."""
+        import torch
+        p = prim0.to(device=self.device, dtype=torch.float64).contiguous()
+        self._prim_keep = p
+        self._check(self.lib.hydro_reset(self.ctx, p.data_ptr(), self.U.data_ptr(), _stream_handle(stream)))
+
+    def loss_eps2(self, U=None, seed=None, scale: float = 1.0, stream=None):
+        """eps2 of U as a device float64 scalar; if seed is a tensor like U it
+        receives scale * d eps2 / dU."""
+        import torch
+        U = self.U if U is None else U
+        out = torch.empty((), dtype=torch.float64, device=self.device)
+        sp = seed.data_ptr() if seed is not None else None
+        self._check(self.lib.hydro_loss_eps2(self.ctx, U.data_ptr(), out.data_ptr(), sp, float(scale),
+                                             _stream_handle(stream)))
+        return out
+
+    def adjoint_step(self, U_ckpt, step0: int, E_jet0, nsteps: int, lam, grad_jets, stream=None):
+        """Reverse sweep over nsteps steps from checkpoint U_ckpt (step step0,
+        jet energies E_jet0); lam (like U) in: dJ/dU(step0+nsteps), out:
+        dJ/dU(step0); grad_jets (njet, 5) float64 device tensor is incremented."""
+        E = (ctypes.c_double * max(1, self.njet))(*[float(v) for v in (E_jet0 if E_jet0 is not None else [])])
+        gp = grad_jets.data_ptr() if grad_jets is not None else None
+        self._check(self.lib.hydro_adjoint_step(self.ctx, U_ckpt.data_ptr(), int(step0), E if self.njet else None,
+                                                int(nsteps), lam.data_ptr(), gp, _stream_handle(stream)))
+
+    def init_vjp(self, prim0, lam, stream=None):
+        """(dU/dprim)^T lam at prim0 (device float64) -> (5, nz, ny, nx) float64."""
+        import torch
+        p = prim0.to(device=self.device, dtype=torch.float64).contiguous()
+        out = torch.empty((5,) + self.shape, dtype=torch.float64, device=self.device)
+        self._check(self.lib.hydro_init_vjp(self.ctx, p.data_ptr(), lam.data_ptr(), out.data_ptr(),
+                                            _stream_handle(stream)))
+        return out
 
     def add_jet(self, x0, dir=(1.0, 0.0, 0.0), E0=50.0, t_start=1.0, kappa_rad=4.0, kappa_coll=2.5,
                 cr_over_cf=1.0) -> int:
