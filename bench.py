@@ -9,8 +9,10 @@ resident in HBM before the timed region starts.
 
 Prints one JSON line: whole-job cell-updates/s (cells x stages / s), the
 roofline of the dominant kernel from HIP events recorded around every
-launch on the launch stream over the timed region, and the CPU oracle timed
-on a bounded slab of the same workload.
+launch on the launch stream over the timed region, the adjoint/forward time
+ratio of the differentiable run (128^3, 100 steps, checkpoints every 10,
+FP32 fields), and the CPU oracle timed on a bounded slab of the stage
+workload.
 
     python bench.py [--steps K] [--warmup W] [--precision f64|f32] [--n 256]
 """
@@ -90,6 +92,47 @@ def cpu_baseline(w, target_s: float):
     }
 
 
+def adjoint_ratio(precision: str, n: int, steps: int, ckpt: int, repeats: int = 3):
+    """Differentiable run (workloads.gradient_event): forward = reset, the
+    steps with a checkpoint every `ckpt` steps, eps2; backward = loss seed,
+    reverse sweep over every segment (recomputing its stage states), initial
+    state VJP.  Best of `repeats` after one untimed pass, GPU-synchronised."""
+    import torch
+    from paper_1511_02137_amd import adjoint as A
+    from paper_1511_02137_amd import workloads as W
+    w = W.gradient_event(n=(n,) * 3, steps=steps)
+    pb = A.Eps2Problem(w, precision=precision, ckpt_every=ckpt)
+    j = w.jets[0]
+    e0 = torch.tensor(w.prim0[0], dtype=torch.float64, device="cuda")
+    tf, tb = [], []
+    for r in range(repeats + 1):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        eps, cks, Uf, prim = pb.forward(e0, j.kappa_rad, j.kappa_coll, j.x0[0], j.x0[1])
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        ge, gj = pb.backward(cks, Uf, prim)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        if r:
+            tf.append(t1 - t0)
+            tb.append(t2 - t1)
+    pb.h.profile(True)
+    pb.backward(cks, Uf, prim)
+    torch.cuda.synchronize()
+    prof = pb.h.profile_read()
+    pb.h.profile(False)
+    g = gj[0].tolist()
+    out = {"workload": "%s: %d^3, %d steps, checkpoint every %d, %s fields, FP64 parameter gradients"
+                       % (w.name, n, steps, ckpt, precision),
+           "forward_ms": 1e3 * min(tf), "backward_ms": 1e3 * min(tb), "ratio": min(tb) / min(tf),
+           "backward_kernels_ms": {k: t for k, (t, c) in prof.items() if c},
+           "eps2": float(eps.item()),
+           "grad": {"kappa_rad": g[0], "kappa_coll": g[1], "x0": g[2], "y0": g[3]}}
+    pb.h.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -100,6 +143,10 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target length of the CPU oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--yz", choices=["tile", "march"], default="tile", help="y/z face kernels")
+    ap.add_argument("--adjoint-n", type=int, default=128, help="grid edge of the differentiable run (0: skip)")
+    ap.add_argument("--adjoint-steps", type=int, default=100)
+    ap.add_argument("--adjoint-ckpt", type=int, default=10)
+    ap.add_argument("--adjoint-precision", choices=["f64", "f32"], default="f32")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain device copy of 1 GiB 10 times (scale for the HBM counters)")
     args = ap.parse_args()
@@ -187,6 +234,10 @@ def main():
     }
     print("timed %d steps: %.3f ms/step, %.3e cell-updates/s" % (args.steps, ms / args.steps, value),
           file=sys.stderr, flush=True)
+    if args.adjoint_n > 0:
+        h.close()
+        out["adjoint"] = adjoint_ratio(args.adjoint_precision, args.adjoint_n, args.adjoint_steps, args.adjoint_ckpt)
+        print("adjoint/forward %.2f" % out["adjoint"]["ratio"], file=sys.stderr, flush=True)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds)
     print(json.dumps(out), flush=True)

@@ -81,6 +81,31 @@ __device__ __forceinline__ PrimJ c2p_jac(double E, double Mx, double My, double 
   return J;
 }
 
+// The same Jacobian for an admissible cell (no fix-up) whose e is known from
+// the recovery: sqrt(4E^2 - 3M^2) = E + e, one division.
+__device__ __forceinline__ PrimJ c2p_jac_known(double E, double Mx, double My, double Mz, double e) {
+  PrimJ J;
+  J.E = E;
+  J.vac = false;
+  J.cap = false;
+  J.capf = 1.0;
+  const double M[3] = {Mx, My, Mz};
+  const double s = E + e;
+  const double W = E + e * (1.0 / 3.0);
+  const double inv = 1.0 / (s * W);
+  const double is = W * inv;
+  J.e = e;
+  J.iW = s * inv;
+  for (int k = 0; k < 3; ++k) {
+    J.Mc[k] = M[k];
+    J.Mh[k] = 0.0;
+    J.v[k] = M[k] * J.iW;
+    J.eM[k] = -3.0 * M[k] * is;
+  }
+  J.eE = 4.0 * E * is - 1.0;
+  return J;
+}
+
 // Given adjoints eb of e and vb of v, the adjoints of (E, M):
 // with Q = (vb . v)/(E + p) and kappa = eb - Q/3:
 //   Eb = kappa de/dE - Q,  Mb_k = kappa de/dM_k + vb_k/(E + p),
@@ -325,6 +350,8 @@ __global__ void __launch_bounds__(TBMAX) k_line_adj(AdjArgs<R> a) {
   // points: lane handles t = tid and t = tid + TB (slot j = padded index + 4)
   int slot[2] = {-1, -1};
   R uo[2][5];
+  double eo[2] = {0.0, 0.0};     // recovered e of the point
+  bool fixed[2] = {false, false};  // the recovery fixed the point up
 #pragma unroll
   for (int q = 0; q < 2; ++q) {
     const int t = tid + q * TB;
@@ -333,7 +360,10 @@ __global__ void __launch_bounds__(TBMAX) k_line_adj(AdjArgs<R> a) {
       slot[q] = j;
       const int src = map_idx(j - 4, n, bc);
       load5(a.W, nc, base + (long long)src * stride, uo[q]);
+      const unsigned f0 = fix;
       const PrimV pv = c2p(uo[q], fix);
+      eo[q] = pv.e;
+      fixed[q] = fix != f0;
       R Fp[5], Fm[5];
       split_flux<R, AX>(uo[q], pv, Fp, Fm);
 #pragma unroll
@@ -409,7 +439,8 @@ __global__ void __launch_bounds__(TBMAX) k_line_adj(AdjArgs<R> a) {
   for (int q = 0; q < 2; ++q) {
     const int j = slot[q];
     if (j < 0) continue;
-    const PrimJ J = c2p_jac((double)uo[q][0], (double)uo[q][1], (double)uo[q][2], (double)uo[q][3]);
+    const double E = (double)uo[q][0], Mx = (double)uo[q][1], My = (double)uo[q][2], Mz = (double)uo[q][3];
+    const PrimJ J = fixed[q] ? c2p_jac(E, Mx, My, Mz) : c2p_jac_known(E, Mx, My, Mz, eo[q]);
     double ap[5], am[5], ub[5];
 #pragma unroll
     for (int c = 0; c < 5; ++c) {
@@ -458,57 +489,106 @@ __global__ void __launch_bounds__(TBMAX) k_line_adj(AdjArgs<R> a) {
   add_fixups(a.fixups, fix);
 }
 
-// Outflow face n-1/2 of every line along AX: phi = -mu(n-1)/dx.  One lane per
-// line; the adjoints of its eight stencil points (ghosts -> cell n-1) are
-// added to G in a fixed order.
+// Outflow face n-1/2 of every line along AX: phi = -mu(n-1)/dx.  A
+// workgroup takes 32 lines: (1) one lane per stencil point computes the split
+// fluxes of the eight points n-4..n+3 (ghosts copy cell n-1); (2) one lane per
+// (line, field, split) reverses that reconstruction; (3) one lane per point
+// reverses the split; (4) one lane per (line, field) adds the eight points'
+// adjoints to their cells in a fixed order.
+constexpr int kBoundLines = 32;
+
 template <class R, int S, int AX>
-__global__ void __launch_bounds__(64) k_bound_adj(AdjArgs<R> a) {
-  __shared__ double sA[64][8][10];
+__global__ void __launch_bounds__(kBoundLines * 10) k_bound_adj(AdjArgs<R> a) {
+  __shared__ R sF[kBoundLines][8][10];        // split fluxes (F+ 0..4, F- 5..9); later the W adjoints [.][.][5]
+  __shared__ double sA[kBoundLines][8][10];   // reconstruction adjoints per point
   const long long nlines = n_lines(AX, a.g);
-  const long long L = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   const int n = a.g.n[AX];
   const long long nc = a.g.nc;
-  const int tl = threadIdx.x;
-  if (L >= nlines) return;  // no barriers below
-  long long stride;
-  const long long base = line_base(AX, L, a.g, stride);
+  const int tid = threadIdx.x;
   unsigned fix = 0;
-  for (int m = 0; m < 8; ++m)
-    for (int k = 0; k < 10; ++k) sA[tl][m][k] = 0.0;
-  for (int c = 0; c < 5; ++c) {
-    R fp[8], fm[8];
-    for (int m = 0; m < 8; ++m) {
+  // (1) split fluxes, lane = (line, point)
+  if (tid < kBoundLines * 8) {
+    const int l = tid >> 3, m = tid & 7;
+    const long long L = (long long)blockIdx.x * kBoundLines + l;
+    if (L < nlines) {
+      long long stride;
+      const long long base = line_base(AX, L, a.g, stride);
       R u[5];
       load5(a.W, nc, base + (long long)map_idx(n - 4 + m, n, 0) * stride, u);
       const PrimV pv = c2p(u, fix);
       R Fp[5], Fm[5];
       split_flux<R, AX>(u, pv, Fp, Fm);
-      fp[m] = Fp[c];
-      fm[m] = Fm[c];
+#pragma unroll
+      for (int c = 0; c < 5; ++c) {
+        sF[l][m][c] = Fp[c];
+        sF[l][m][5 + c] = Fm[c];
+      }
     }
-    const R phi = -a.mu[c * nc + base + (long long)(n - 1) * stride] * a.inv_d;
-    R args[7], ab[7];
-    for (int m = 0; m < 7; ++m) args[m] = fp[m];
-    weno7_vjp<R, S>(args, phi, a.eps, ab);
-    for (int m = 0; m < 7; ++m) sA[tl][m][c] += (double)ab[m];
-    for (int m = 0; m < 7; ++m) args[m] = fm[7 - m];
-    weno7_vjp<R, S>(args, phi, a.eps, ab);
-    for (int m = 0; m < 7; ++m) sA[tl][7 - m][5 + c] += (double)ab[m];
   }
-  for (int m = 0; m < 8; ++m) {
-    const int cell = map_idx(n - 4 + m, n, 0);
-    R u[5];
-    load5(a.W, nc, base + (long long)cell * stride, u);
+  __syncthreads();
+  // (2) reconstruction adjoints, lane = (line, field, split)
+  {
+    const int l = tid / 10, r = tid % 10, c = r >> 1, sp = r & 1;
+    const long long L = (long long)blockIdx.x * kBoundLines + l;
+    if (L < nlines) {
+      long long stride;
+      const long long base = line_base(AX, L, a.g, stride);
+      const R phi = -a.mu[c * nc + base + (long long)(n - 1) * stride] * a.inv_d;
+      R args[7], ab[7];
+      if (sp == 0) {
+#pragma unroll
+        for (int m = 0; m < 7; ++m) args[m] = sF[l][m][c];
+        weno7_vjp<R, S>(args, phi, a.eps, ab);
+#pragma unroll
+        for (int m = 0; m < 7; ++m) sA[l][m][c] = (double)ab[m];
+        sA[l][7][c] = 0.0;
+      } else {
+#pragma unroll
+        for (int m = 0; m < 7; ++m) args[m] = sF[l][7 - m][5 + c];
+        weno7_vjp<R, S>(args, phi, a.eps, ab);
+#pragma unroll
+        for (int m = 0; m < 7; ++m) sA[l][7 - m][5 + c] = (double)ab[m];
+        sA[l][0][5 + c] = 0.0;
+      }
+    }
+  }
+  __syncthreads();
+  // (3) split-flux adjoint per point, lane = (line, point); result over sF
+  R u[5];
+  double ub[5];
+  const int l3 = tid >> 3, m3 = tid & 7;
+  const long long L3 = (long long)blockIdx.x * kBoundLines + l3;
+  const bool act3 = tid < kBoundLines * 8 && L3 < nlines;
+  if (act3) {
+    long long stride;
+    const long long base = line_base(AX, L3, a.g, stride);
+    load5(a.W, nc, base + (long long)map_idx(n - 4 + m3, n, 0) * stride, u);
     const PrimJ J = c2p_jac((double)u[0], (double)u[1], (double)u[2], (double)u[3]);
-    double ap[5], am[5], ub[5];
+    double ap[5], am[5];
+#pragma unroll
     for (int c = 0; c < 5; ++c) {
-      ap[c] = sA[tl][m][c];
-      am[c] = sA[tl][m][5 + c];
+      ap[c] = sA[l3][m3][c];
+      am[c] = sA[l3][m3][5 + c];
     }
     split_flux_vjp<R, AX>(u, J, ap, am, ub);
-    for (int c = 0; c < 5; ++c) {
-      R* gp = a.G + c * nc + base + (long long)cell * stride;
-      *gp = *gp + (R)ub[c];
+  }
+  __syncthreads();  // every lane has read sF/sA
+  if (act3) {
+#pragma unroll
+    for (int c = 0; c < 5; ++c) sF[l3][m3][c] = (R)ub[c];
+  }
+  __syncthreads();
+  // (4) add to G, lane = (line, field), points in order
+  if (tid < kBoundLines * 5) {
+    const int l = tid / 5, c = tid % 5;
+    const long long L = (long long)blockIdx.x * kBoundLines + l;
+    if (L < nlines) {
+      long long stride;
+      const long long base = line_base(AX, L, a.g, stride);
+      for (int m = 0; m < 8; ++m) {
+        R* gp = a.G + c * nc + base + (long long)map_idx(n - 4 + m, n, 0) * stride;
+        *gp = *gp + sF[l][m][c];
+      }
     }
   }
   add_fixups(a.fixups, fix);
@@ -787,10 +867,11 @@ __global__ void __launch_bounds__(256) k_prim_vjp(const double* __restrict__ pri
 // Host-side launchers.
 template <class R, int S>
 void launch_bound_adj(int AX, const AdjArgs<R>& a, long long nl, hipStream_t st) {
-  const unsigned nbb = (unsigned)((nl + 63) / 64);
-  if (AX == 0) hipLaunchKernelGGL((k_bound_adj<R, S, 0>), dim3(nbb), dim3(64), 0, st, a);
-  if (AX == 1) hipLaunchKernelGGL((k_bound_adj<R, S, 1>), dim3(nbb), dim3(64), 0, st, a);
-  if (AX == 2) hipLaunchKernelGGL((k_bound_adj<R, S, 2>), dim3(nbb), dim3(64), 0, st, a);
+  const unsigned nbb = (unsigned)((nl + kBoundLines - 1) / kBoundLines);
+  const dim3 tb(kBoundLines * 10);
+  if (AX == 0) hipLaunchKernelGGL((k_bound_adj<R, S, 0>), dim3(nbb), tb, 0, st, a);
+  if (AX == 1) hipLaunchKernelGGL((k_bound_adj<R, S, 1>), dim3(nbb), tb, 0, st, a);
+  if (AX == 2) hipLaunchKernelGGL((k_bound_adj<R, S, 2>), dim3(nbb), tb, 0, st, a);
 }
 
 template <class R, int S>
