@@ -245,3 +245,29 @@ def test_32cube_gradients_match_complex_step():
     got = float(np.sum(g["e_init"] * de))
     print("32^3 e_init direction: gpu %.15e oracle %.15e, conditioning bar %.3e" % (got, ref, bar / abs(ref)))
     assert abs(got - ref) <= bar, (got, ref, bar)
+
+
+def test_differentiable_run_matches_full_size_complex_step_fixture():
+    """128^3, 100 steps, checkpoints every 10: FP64 adjoint against the
+    oracle's complex-step gradients stored in tests/golden (written by
+    tests/golden/make_gradient_golden.py from the oracle alone); the FP32
+    form against the same values with its stated error."""
+    import json
+    import os
+    gold = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "gradient_event_128.json")))
+    w = W.gradient_event()
+    assert w.name == gold["workload"] and w.steps == gold["steps"]
+    g64 = gpu_grads(w, "f64", ckpt=10)
+    assert abs(g64["eps2"] - gold["eps2"]) <= 1e-12 * abs(gold["eps2"])
+    for k, which in enumerate(PARAMS):
+        ref = gold["grad"][which]
+        assert abs(g64["jets"][0, k] - ref) <= 1e-9 * abs(ref), (which, g64["jets"][0, k], ref)
+    g32 = gpu_grads(w, "f32", ckpt=10)
+    assert abs(g32["eps2"] - gold["eps2"]) <= 1e-6 * abs(gold["eps2"])
+    # FP32 fields, FP64 gradient accumulation: kappa gradients to 1e-4, origin
+    # gradients to 2e-2 (measured 2e-5, 1e-5, 7e-5, 5e-3)
+    for k, (which, bar) in enumerate(zip(PARAMS, (1e-4, 1e-4, 2e-2, 2e-2))):
+        ref = gold["grad"][which]
+        rel = abs(g32["jets"][0, k] - ref) / abs(ref)
+        print("FP32 %s: rel %.2e" % (which, rel))
+        assert rel <= bar, (which, rel)
