@@ -11,8 +11,8 @@ Prints one JSON line: whole-job cell-updates/s (cells x stages / s), the
 roofline of the dominant kernel from HIP events recorded around every
 launch on the launch stream over the timed region, the adjoint/forward time
 ratio of the differentiable run (128^3, 100 steps, checkpoints every 10,
-FP32 fields), and the CPU oracle timed on a bounded slab of the stage
-workload.
+FP32 fields), the throughput of the 64-event uneven ensemble through the
+batch API, and the CPU oracle timed on a bounded slab of the stage workload.
 
     python bench.py [--steps K] [--warmup W] [--precision f64|f32] [--n 256]
 """
@@ -133,6 +133,35 @@ def adjoint_ratio(precision: str, n: int, steps: int, ckpt: int, repeats: int = 
     return out
 
 
+def batch_throughput(precision: str, steps: int, warmup: int, cache):
+    """The uneven ensemble (workloads.ensemble: 64 events, edges 64/96/128,
+    0-3 jets) advanced by the batch API: autotuned launch shapes, one graph
+    replay per step; cell-updates/s over `steps` steps."""
+    import torch
+    from paper_1511_02137_amd import hydro as H
+    from paper_1511_02137_amd import workloads as W
+    ws = W.ensemble(steps=steps)
+    b = H.batch_from_workloads(ws, precision=precision)
+    from_cache = b.autotune(cache)
+    b.run(warmup)
+    torch.cuda.synchronize()
+    start = torch.cuda.Event(enable_timing=True)
+    stop = torch.cuda.Event(enable_timing=True)
+    start.record()
+    b.run(steps)
+    stop.record()
+    torch.cuda.synchronize()
+    ms = start.elapsed_time(stop)
+    cells = sum(w.n[0] * w.n[1] * w.n[2] for w in ws)
+    out = {"workload": "ensemble of %d events, edges {64, 96, 128} per axis, 0-3 jets, %s fields, %d steps, "
+                       "one graph replay per step" % (len(ws), precision, steps),
+           "cells": cells, "ms_per_step": ms / steps, "value": cells * 3 * steps / (ms * 1e-3),
+           "unit": "cell-updates/s", "blocks_per_axis": [b.get_option(a) for a in (0, 1, 2)],
+           "tuned_from_cache": from_cache, "fixups": b.fixups()}
+    b.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -147,6 +176,9 @@ def main():
     ap.add_argument("--adjoint-steps", type=int, default=100)
     ap.add_argument("--adjoint-ckpt", type=int, default=10)
     ap.add_argument("--adjoint-precision", choices=["f64", "f32"], default="f32")
+    ap.add_argument("--batch-steps", type=int, default=50, help="steps of the ensemble run (0: skip)")
+    ap.add_argument("--batch-precision", choices=["f64", "f32"], default="f32")
+    ap.add_argument("--tune-cache", default=None, help="autotuner cache file of the ensemble run")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain device copy of 1 GiB 10 times (scale for the HBM counters)")
     args = ap.parse_args()
@@ -238,6 +270,9 @@ def main():
         h.close()
         out["adjoint"] = adjoint_ratio(args.adjoint_precision, args.adjoint_n, args.adjoint_steps, args.adjoint_ckpt)
         print("adjoint/forward %.2f" % out["adjoint"]["ratio"], file=sys.stderr, flush=True)
+    if args.batch_steps > 0:
+        out["batch"] = batch_throughput(args.batch_precision, args.batch_steps, 2, args.tune_cache)
+        print("batch %.3e cell-updates/s" % out["batch"]["value"], file=sys.stderr, flush=True)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds)
     print(json.dumps(out), flush=True)

@@ -201,7 +201,8 @@ int hydro_init_vjp(hydro_ctx* ctx, const double* prim0, const void* lambda, doub
  * variant computes each face with the same arithmetic). */
 typedef enum {
   HYDRO_OPT_YZ_KERNEL = 0,  /* y/z faces: 0 = LDS tiles (default), 1 = register marches */
-  HYDRO_OPT_MARCH_SEG = 1   /* cells per march segment (default 32) */
+  HYDRO_OPT_MARCH_SEG = 1,  /* cells per march segment (default 32) */
+  HYDRO_OPT_X_KERNEL = 2    /* x faces: 0 = one row per workgroup (default), 1 = 32 x 16 LDS tiles */
 } hydro_option;
 
 /* Set / read an option; HYDRO_EINVAL for an unknown option or bad value. */
@@ -234,6 +235,80 @@ int hydro_profile_read(hydro_ctx* ctx, double* ms, int64_t* launches, int nk);
 const char* hydro_last_error(const hydro_ctx* ctx);
 
 void hydro_destroy(hydro_ctx* ctx);
+
+/* ------------------------------------------------------------------------
+ * Batches: many independent events (each its own grid, spacing, times,
+ * boundaries, deposit and jets) advanced together, as an ensemble of the
+ * paper's problem.  The events must share precision, weno, weno_eps and
+ * weno_p.  Per RK stage there is one launch per axis whose workgroups walk
+ * the tiles of every event (x: 32 x 16 cells, y and z: 16 x 32), one launch
+ * for the jets of every event, and per step one FP64 reduction launch; each
+ * face is computed with the same arithmetic as hydro_rk3_step, so every
+ * event evolves exactly as it would alone.  Stage times come from a device
+ * step counter; the launches of one step are captured once into a HIP graph
+ * that hydro_batch_run replays.
+ * ------------------------------------------------------------------------ */
+typedef struct hydro_batch hydro_batch;
+
+/* Device workspace for a batch: per event two stage states and one
+ * divergence field (15 words per cell), each block 256-byte aligned.
+ * Returns 0 for an invalid or incompatible list. */
+size_t hydro_batch_workspace_bytes(const hydro_config* cfgs, int n_events);
+
+/* Create a batch.
+ *   cfgs[n_events]   per-event configurations (host).
+ *   prim0            NULL, or [n_events] pointers (each NULL or FP64
+ *                    primitives [5][nz][ny][nx] in host or device memory,
+ *                    as in hydro_init); NULL entries leave U[e] as is.
+ *   U[n_events]      caller-owned device states, written from prim0.
+ *   workspace        device, >= hydro_batch_workspace_bytes, 256-aligned,
+ *                    caller-owned, used until destroy.
+ * All events start at step 0 with no jets.  Errors: hydro_batch_last_error(NULL). */
+int hydro_batch_create(const hydro_config* cfgs, int n_events, const double* const* prim0, void* const* U,
+                       void* workspace, size_t ws_bytes, void* stream, hydro_batch** out);
+
+/* Append a jet to event `event` (synchronous; checks as hydro_add_jet). */
+int hydro_batch_add_jet(hydro_batch* b, int event, const hydro_jet* jet, int* jet_id);
+
+/* Advance every event by nsteps SSP-RK3 steps (as hydro_rk3_step, including
+ * the jet energies, ledgers and FP64 sums of each event). */
+int hydro_batch_run(hydro_batch* b, int nsteps, void* stream);
+
+/* Right-hand side L = D + S of every event at its current time into its
+ * first stage buffer (workspace); no state changes.  For timing/tuning. */
+int hydro_batch_rhs(hydro_batch* b, void* stream);
+
+/* Launch-shape options of a batch (results do not depend on them). */
+typedef enum {
+  HYDRO_BOPT_BLOCKS_X = 0,  /* workgroups of the x launch: 0 = one per tile, else a persistent grid */
+  HYDRO_BOPT_BLOCKS_Y = 1,
+  HYDRO_BOPT_BLOCKS_Z = 2,
+  HYDRO_BOPT_GRAPH = 3      /* 1 (default): replay a captured graph per step; 0: direct launches */
+} hydro_batch_option;
+
+int hydro_batch_set_option(hydro_batch* b, int option, long long value);
+int hydro_batch_get_option(hydro_batch* b, int option, long long* value);
+
+/* Pick the workgroup count of each axis launch: the candidates 0 (one per
+ * tile) and c * (number of CUs), c in {1, 2, 3, 4, 6, 8}, are timed on this
+ * batch (median of 5 launches of the right-hand-side form, no state change)
+ * and the fastest kept.  cache_path (may be NULL) is a text file of
+ * "key bx by bz" lines, the key a hash of the GPU, precision, scheme and the
+ * sorted event shapes: a hit skips the timing (*from_cache = 1), a miss
+ * appends the picks.  Synchronous. */
+int hydro_batch_autotune(hydro_batch* b, const char* cache_path, void* stream, int* from_cache);
+
+/* Synchronous: sums of event `event` as hydro_sums (ledger in out[5]). */
+int hydro_batch_sums(hydro_batch* b, int event, double out[6]);
+
+/* Synchronous: time, step and the remaining jet energies of one event. */
+int hydro_batch_get_state(hydro_batch* b, int event, double* t, int64_t* step, double* E_jet, int n_jet);
+
+/* Synchronous: conserved->primitive fix-ups of all events. */
+int hydro_batch_diag(hydro_batch* b, int64_t* fixups);
+
+const char* hydro_batch_last_error(const hydro_batch* b);
+void hydro_batch_destroy(hydro_batch* b);
 
 #ifdef __cplusplus
 }

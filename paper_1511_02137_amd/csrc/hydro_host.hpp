@@ -1,0 +1,104 @@
+// hydro_host.hpp -- host-side helpers shared by the single-event API
+// (hydro_api.hip) and the batch API (hydro_batch.hip): configuration checks,
+// grid set-up, and the declarations of the kernel launchers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <string>
+
+#include "hydro.h"
+#include "hydro_internal.hpp"
+
+namespace hydro {
+
+inline size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+inline size_t elem_size(const hydro_config* c) { return c->precision == HYDRO_F32 ? sizeof(float) : sizeof(double); }
+
+inline long long ncells(const hydro_config* c) { return (long long)c->n[0] * c->n[1] * c->n[2]; }
+
+inline bool config_ok(const hydro_config* c, std::string* why) {
+  auto fail = [&](const char* m) {
+    if (why) *why = m;
+    return false;
+  };
+  if (!c) return fail("config is NULL");
+  for (int d = 0; d < 3; ++d) {
+    if (c->n[d] < 1) return fail("n[d] must be >= 1");
+    if (!(c->dx[d] > 0.0) || !std::isfinite(c->dx[d])) return fail("dx[d] must be > 0");
+    if (c->bc[d] != HYDRO_BC_OUTFLOW && c->bc[d] != HYDRO_BC_PERIODIC) return fail("bad bc");
+  }
+  if (c->n[0] > 1024) return fail("n[0] must be <= 1024");
+  // the x-face kernel keeps the split fluxes of one row (+8 ghosts) in LDS
+  if ((size_t)10 * (c->n[0] + 8) * elem_size(c) > 65536) return fail("n[0] too large for the x-row LDS tile");
+  if ((long long)c->n[1] * c->n[2] > 2147483647LL) return fail("too many rows");
+  if (c->n[1] > 65535 || c->n[2] > 65535) return fail("n[1], n[2] must be <= 65535");
+  if (!(c->dt > 0.0) || !std::isfinite(c->dt) || !std::isfinite(c->t0)) return fail("dt must be > 0");
+  if (c->precision != HYDRO_F64 && c->precision != HYDRO_F32) return fail("bad precision");
+  if (c->weno < 0 || c->weno > 2) return fail("bad weno");
+  if (c->deposit != HYDRO_DEP_NGP && c->deposit != HYDRO_DEP_GAUSS) return fail("bad deposit");
+  if (!(c->weno_eps > 0.0)) return fail("weno_eps must be > 0");
+  if (c->weno_p != 2) return fail("only weno_p = 2 is built");
+  if (!(c->eos_dof > 0.0) || !(c->hbarc > 0.0)) return fail("eos_dof and hbarc must be > 0");
+  return true;
+}
+
+inline Grid make_grid(const hydro_config* c) {
+  Grid g;
+  for (int d = 0; d < 3; ++d) {
+    g.n[d] = c->n[d];
+    g.bc[d] = c->bc[d];
+    g.dx[d] = c->dx[d];
+  }
+  g.nc = ncells(c);
+  return g;
+}
+
+inline bool is_device_pointer(const void* p) {
+  hipPointerAttribute_t attr;
+  hipError_t e = hipPointerGetAttributes(&attr, p);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return false;
+  }
+  return attr.type == hipMemoryTypeDevice;
+}
+
+// Launchers (hydro_kernels.hip, hydro_adjoint.hip).
+template <class R>
+hipError_t launch_face_kernel(int kernel, const StageArgs<R>& a, int scheme, int seg, hipStream_t st);
+template <class R>
+hipError_t launch_jet(const JetArgs& a, hipStream_t st);
+template <class R>
+hipError_t launch_sums(const R* U, long long nc, double dV, double* part, DevScalars* s, hipStream_t st);
+template <class R>
+hipError_t launch_prim_to_cons(const double* prim, R* U, long long nc, hipStream_t st);
+template <class R>
+hipError_t launch_primitives(const R* U, R* prim, long long nc, double g, double hc, unsigned long long* fixups,
+                             hipStream_t st);
+template <class R>
+hipError_t launch_adj_axis(int AX, const AdjArgs<R>& a, int scheme, hipStream_t st);
+template <class R>
+hipError_t launch_jet_adj(const JetAdjArgs& a, hipStream_t st);
+template <class R>
+hipError_t launch_copy(const R* src, R* dst, long long n, hipStream_t st);
+hipError_t launch_copy_f64(const double* src, double* dst, int n, hipStream_t st);
+template <class R>
+hipError_t launch_fill(R* dst, long long n, R v, hipStream_t st);
+template <class R>
+hipError_t launch_eps2(const R* U, const Grid& g, double* part, double* out3, hipStream_t st);
+template <class R>
+hipError_t launch_eps2_seed(const R* U, const Grid& g, const double* out3, R* lam, double scale, hipStream_t st);
+template <class R>
+hipError_t launch_prim_vjp(const double* prim, const R* lam, double* out, long long nc, hipStream_t st);
+template <class R>
+hipError_t launch_batch_axis(int AX, const BatchArgs<R>& b, int scheme, long long blocks, hipStream_t st);
+template <class R>
+hipError_t launch_batch_jet(const BatchArgs<R>& b, hipStream_t st);
+template <class R>
+hipError_t launch_batch_sums(const BatchArgs<R>& b, long long* step, hipStream_t st);
+long long batch_items(int AX, const Grid& g);
+
+}  // namespace hydro

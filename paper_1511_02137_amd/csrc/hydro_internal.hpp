@@ -71,6 +71,36 @@ struct JetArgs {
   double eos_dof, hbarc;
 };
 
+// One event of a batch (device table, see hydro_batch.hip).
+struct BatchEvent {
+  Grid g;
+  void* U;            // caller's state [5][nc]
+  void* U1;           // stage states and divergence (workspace)
+  void* U2;
+  void* D;
+  double* part;       // reduction partials [kSumBlocks][5]
+  DevScalars* dev;    // jets, E_jet, ledger, sums, fix-ups
+  double t0, dt;
+  double inv_d[3];    // 1/dx per axis
+  double dV;
+  double eos_dof, hbarc;
+  int njet;
+  int deposit;
+};
+
+// Arguments of the batched kernels: the work items of one axis are the tiles
+// of every event in event order; off[e] is the first item of event e.
+template <class R>
+struct BatchArgs {
+  const BatchEvent* ev;
+  const long long* off;   // [n_events + 1] for the launched axis
+  long long items;        // off[n_events]
+  const long long* step;  // device step counter (stage times)
+  int n_events;
+  int stage;              // 1..3; 0: L written to U1 (no state change)
+  R eps;
+};
+
 // Arguments of the line adjoint kernels (device pointers).
 template <class R>
 struct AdjArgs {

@@ -228,9 +228,7 @@ constexpr int kTileP = kTileA + 8;   // points along AX
 constexpr int kTileXP = kTileX;      // x pitch of the LDS arrays (128-byte rows)
 
 template <class R, int S, int AX, bool LAST>
-__global__ void __launch_bounds__(512) k_tile(StageArgs<R> a) {
-  extern __shared__ __align__(16) unsigned char smem_raw[];
-  R* s = reinterpret_cast<R*>(smem_raw);
+__device__ __forceinline__ void tile_body(const StageArgs<R>& a, int bx, int by, int bz, R* s) {
   R* sFp = s;                              // [5][kTileP][kTileXP]
   R* sFm = s + 5 * kTileP * kTileXP;       // [5][kTileP][kTileXP]
   const int nx = a.g.n[0], ny = a.g.n[1];
@@ -239,9 +237,9 @@ __global__ void __launch_bounds__(512) k_tile(StageArgs<R> a) {
   const long long nc = a.g.nc;
   const int tx = threadIdx.x & (kTileX - 1);
   const int ta = threadIdx.x >> 4;  // 0..31
-  const int x = blockIdx.x * kTileX + tx;
-  const int a0 = blockIdx.y * kTileA;
-  const int o = blockIdx.z;
+  const int x = bx * kTileX + tx;
+  const int a0 = by * kTileA;
+  const int o = bz;
   const long long stride = (AX == 1) ? (long long)nx : (long long)nx * ny;
   const long long base = (AX == 1) ? (long long)o * nx * ny + x : (long long)o * nx + x;
   const bool xin = x < nx;
@@ -351,10 +349,119 @@ __global__ void __launch_bounds__(512) k_tile(StageArgs<R> a) {
   add_fixups(a.fixups, fix);
 }
 
+
+template <class R, int S, int AX, bool LAST>
+__global__ void __launch_bounds__(512) k_tile(StageArgs<R> a) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  tile_body<R, S, AX, LAST>(a, blockIdx.x, blockIdx.y, blockIdx.z, reinterpret_cast<R*>(smem_raw));
+}
+
+// ---------------------------------------------------------------------------
+// x-faces from an LDS tile: a workgroup of 512 lanes owns 32 cells along x by
+// 16 rows along y at one z.  The 40 x 16 points (4 ghosts on each side) are
+// loaded x-fastest (coalesced) and their split x-fluxes stored [c][x][y], so a
+// face lane (y fastest) reads them without bank conflicts; the 33 face rows
+// are reconstructed (one face per lane, one extra row for 16 lanes) and the
+// divergence is formed with lanes x-fastest again and assigned to D (x is the
+// first axis).  Same per-face arithmetic as k_xface + k_xbound.
+constexpr int kXTileX = 32;
+constexpr int kXTileY = 16;
+constexpr int kXTileP = kXTileX + 8;
+constexpr int kXFacePitch = kXTileY + 1;
+
+template <class R, int S>
+__device__ __forceinline__ void xtile_body(const StageArgs<R>& a, int bx, int by, int bz, R* s) {
+  R* sFp = s;                                // [5][kXTileP][kXTileY]
+  R* sFm = s + 5 * kXTileP * kXTileY;        // [5][kXTileP][kXTileY]
+  const int nx = a.g.n[0], ny = a.g.n[1];
+  const int bc = a.g.bc[0];
+  const long long nc = a.g.nc;
+  const int x0 = bx * kXTileX, y0 = by * kXTileY;
+  const long long zbase = (long long)bz * nx * ny;
+  unsigned fix = 0;
+  for (int t = threadIdx.x; t < kXTileP * kXTileY; t += 512) {
+    const int j = t % kXTileP, r = t / kXTileP;
+    const int y = y0 + r;
+    if (y < ny) {
+      R u[5];
+      load5(a.W, nc, zbase + (long long)y * nx + map_idx(x0 - 4 + j, nx, bc), u);
+      const PrimV pv = c2p(u, fix);
+      R Fp[5], Fm[5];
+      split_flux<R, 0>(u, pv, Fp, Fm);
+#pragma unroll
+      for (int c = 0; c < 5; ++c) {
+        sFp[(c * kXTileP + j) * kXTileY + r] = Fp[c];
+        sFm[(c * kXTileP + j) * kXTileY + r] = Fm[c];
+      }
+    }
+  }
+  __syncthreads();
+
+  // faces f = 0..32: face (x0 - 1 + f) + 1/2; F+ at slots f..f+6, F- at f+1..f+7
+  const int r = threadIdx.x & (kXTileY - 1);
+  const int f = threadIdx.x >> 4;  // 0..31
+  const int nf = min(kXTileX, nx - x0) + 1;
+  const bool yin = y0 + r < ny;
+  const bool has1 = yin && f < nf;
+  const bool has2 = yin && threadIdx.x < kXTileY && kXTileX < nf;
+  R Fh[5], Fh2[5];
+  if (has1) {
+#pragma unroll
+    for (int c = 0; c < 5; ++c) {
+      const R* fp = sFp + (c * kXTileP + f) * kXTileY + r;
+      const R* fm = sFm + (c * kXTileP + f) * kXTileY + r;
+      Fh[c] = weno7<R, S>(fp[0], fp[kXTileY], fp[2 * kXTileY], fp[3 * kXTileY], fp[4 * kXTileY], fp[5 * kXTileY],
+                          fp[6 * kXTileY], a.eps) +
+              weno7<R, S>(fm[7 * kXTileY], fm[6 * kXTileY], fm[5 * kXTileY], fm[4 * kXTileY], fm[3 * kXTileY],
+                          fm[2 * kXTileY], fm[kXTileY], a.eps);
+    }
+  }
+  if (has2) {
+#pragma unroll
+    for (int c = 0; c < 5; ++c) {
+      const R* fp = sFp + (c * kXTileP + kXTileX) * kXTileY + r;
+      const R* fm = sFm + (c * kXTileP + kXTileX) * kXTileY + r;
+      Fh2[c] = weno7<R, S>(fp[0], fp[kXTileY], fp[2 * kXTileY], fp[3 * kXTileY], fp[4 * kXTileY], fp[5 * kXTileY],
+                           fp[6 * kXTileY], a.eps) +
+               weno7<R, S>(fm[7 * kXTileY], fm[6 * kXTileY], fm[5 * kXTileY], fm[4 * kXTileY], fm[3 * kXTileY],
+                           fm[2 * kXTileY], fm[kXTileY], a.eps);
+    }
+  }
+  __syncthreads();
+  R* sF = s;  // [5][kXTileX + 1][kXFacePitch]
+  if (has1) {
+#pragma unroll
+    for (int c = 0; c < 5; ++c) sF[(c * (kXTileX + 1) + f) * kXFacePitch + r] = Fh[c];
+  }
+  if (has2) {
+#pragma unroll
+    for (int c = 0; c < 5; ++c) sF[(c * (kXTileX + 1) + kXTileX) * kXFacePitch + r] = Fh2[c];
+  }
+  __syncthreads();
+
+  const int xa = threadIdx.x & (kXTileX - 1), ra = threadIdx.x >> 5;
+  if (x0 + xa < nx && y0 + ra < ny) {
+    const long long cell = zbase + (long long)(y0 + ra) * nx + x0 + xa;
+#pragma unroll
+    for (int c = 0; c < 5; ++c) {
+      const R l = sF[(c * (kXTileX + 1) + xa) * kXFacePitch + ra];
+      const R rr = sF[(c * (kXTileX + 1) + xa + 1) * kXFacePitch + ra];
+      a.D[c * nc + cell] = (l - rr) * a.inv_d;
+    }
+  }
+  add_fixups(a.fixups, fix);
+}
+
+template <class R, int S>
+__global__ void __launch_bounds__(512) k_xtile(StageArgs<R> a) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  xtile_body<R, S>(a, blockIdx.x, blockIdx.y, blockIdx.z, reinterpret_cast<R*>(smem_raw));
+}
+
 // ---------------------------------------------------------------------------
 // Jet source (Eq. 2 and 3).  One workgroup of 512 threads; jets in order.
 template <class R>
-__global__ void __launch_bounds__(512) k_jet(JetArgs a) {
+__device__ __forceinline__ void jet_body(const JetArgs& a) {
   const R* W = static_cast<const R*>(a.W);
   R* D = static_cast<R*>(a.D);
   const long long nc = a.g.nc;
@@ -455,6 +562,11 @@ __global__ void __launch_bounds__(512) k_jet(JetArgs a) {
   add_fixups(&a.s->fixups, fix);
 }
 
+template <class R>
+__global__ void __launch_bounds__(512) k_jet(JetArgs a) {
+  jet_body<R>(a);
+}
+
 // ---------------------------------------------------------------------------
 // FP64 sums of the five fields, fixed order: per-block partials, then one block.
 __device__ __forceinline__ double wave_sum(double v) {
@@ -464,9 +576,9 @@ __device__ __forceinline__ double wave_sum(double v) {
 }
 
 template <class R>
-__global__ void __launch_bounds__(256) k_sums_partial(const R* __restrict__ U, long long nc, double* part) {
+__device__ __forceinline__ void sums_partial_body(const R* __restrict__ U, long long nc, double* part, int b, int nb) {
   double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
-  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < nc; i += (long long)gridDim.x * blockDim.x) {
+  for (long long i = (long long)b * blockDim.x + threadIdx.x; i < nc; i += (long long)nb * blockDim.x) {
 #pragma unroll
     for (int c = 0; c < 5; ++c) acc[c] += (double)U[c * nc + i];
   }
@@ -480,11 +592,16 @@ __global__ void __launch_bounds__(256) k_sums_partial(const R* __restrict__ U, l
   __syncthreads();
   if (threadIdx.x < 5) {
     const int c = threadIdx.x;
-    part[(long long)blockIdx.x * 5 + c] = (red[c][0] + red[c][1]) + (red[c][2] + red[c][3]);
+    part[(long long)b * 5 + c] = (red[c][0] + red[c][1]) + (red[c][2] + red[c][3]);
   }
 }
 
-__global__ void __launch_bounds__(256) k_sums_final(const double* part, int nblocks, double dV, DevScalars* s) {
+template <class R>
+__global__ void __launch_bounds__(256) k_sums_partial(const R* __restrict__ U, long long nc, double* part) {
+  sums_partial_body<R>(U, nc, part, blockIdx.x, gridDim.x);
+}
+
+__device__ __forceinline__ void sums_final_body(const double* part, int nblocks, double dV, DevScalars* s) {
   __shared__ double red[5][4];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   for (int c = 0; c < 5; ++c) {
@@ -498,6 +615,10 @@ __global__ void __launch_bounds__(256) k_sums_final(const double* part, int nblo
     const int c = threadIdx.x;
     s->sums[c] = ((red[c][0] + red[c][1]) + (red[c][2] + red[c][3])) * dV;
   }
+}
+
+__global__ void __launch_bounds__(256) k_sums_final(const double* part, int nblocks, double dV, DevScalars* s) {
+  sums_final_body(part, nblocks, dV, s);
 }
 
 // ---------------------------------------------------------------------------
@@ -538,6 +659,106 @@ __global__ void __launch_bounds__(256) k_primitives(const R* __restrict__ U, R* 
     prim[5 * nc + q] = (R)temperature(pv.e, g, hc);
   }
   add_fixups(fixups, fix);
+}
+
+// ---------------------------------------------------------------------------
+// Batched stage kernels.  Each workgroup walks the work items blockIdx.x,
+// blockIdx.x + gridDim.x, ... (persistent when the grid is smaller than the
+// item count); an item is one tile of one event and runs the same body as the
+// single-event kernel, so every face has the same arithmetic.
+__device__ __forceinline__ int batch_event_of(const long long* off, int n, long long item) {
+  int lo = 0, hi = n;  // off[lo] <= item < off[hi]
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (off[mid] <= item) lo = mid;
+    else hi = mid;
+  }
+  return lo;
+}
+
+template <class R>
+__device__ __forceinline__ StageArgs<R> batch_stage_args(const BatchEvent& ev, int stage, R eps, int AX) {
+  StageArgs<R> a;
+  R* U = static_cast<R*>(ev.U);
+  R* U1 = static_cast<R*>(ev.U1);
+  R* U2 = static_cast<R*>(ev.U2);
+  a.W = (stage <= 1) ? U : (stage == 2 ? U1 : U2);
+  a.Un = U;
+  a.out = (stage <= 1) ? U1 : (stage == 2 ? U2 : U);
+  a.D = static_cast<R*>(ev.D);
+  a.g = ev.g;
+  a.inv_d = (R)ev.inv_d[AX];
+  a.dt = (R)ev.dt;
+  a.eps = eps;
+  a.stage = stage;
+  a.seg = 0;
+  a.fixups = &ev.dev->fixups;
+  return a;
+}
+
+__device__ __forceinline__ double batch_stage_time(const BatchEvent& ev, long long step, int stage) {
+  const double tn = ev.t0 + (double)step * ev.dt;
+  const double c = stage == 2 ? 1.0 : (stage == 3 ? 0.5 : 0.0);
+  return tn + c * ev.dt;
+}
+
+template <class R, int S, int AX>
+__global__ void __launch_bounds__(512) k_btile(BatchArgs<R> b) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  R* s = reinterpret_cast<R*>(smem_raw);
+  for (long long it = blockIdx.x; it < b.items; it += gridDim.x) {
+    const int e = batch_event_of(b.off, b.n_events, it);
+    const BatchEvent& ev = b.ev[e];
+    const long long local = it - b.off[e];
+    const StageArgs<R> a = batch_stage_args<R>(ev, b.stage, b.eps, AX);
+    if (AX == 0) {
+      const int gx = (ev.g.n[0] + kXTileX - 1) / kXTileX, gy = (ev.g.n[1] + kXTileY - 1) / kXTileY;
+      xtile_body<R, S>(a, (int)(local % gx), (int)((local / gx) % gy), (int)(local / ((long long)gx * gy)), s);
+    } else {
+      const int gx = (ev.g.n[0] + kTileX - 1) / kTileX, ga = (ev.g.n[AX] + kTileA - 1) / kTileA;
+      tile_body<R, S, AX, AX == 2>(a, (int)(local % gx), (int)((local / gx) % ga),
+                                   (int)(local / ((long long)gx * ga)), s);
+    }
+    __syncthreads();  // the next item overwrites the LDS tile
+  }
+}
+
+// Jets of every event: one workgroup per event.
+template <class R>
+__global__ void __launch_bounds__(512) k_bjet(BatchArgs<R> b) {
+  const BatchEvent& ev = b.ev[blockIdx.x];
+  if (ev.njet == 0) return;  // whole workgroup
+  const int stage = b.stage;
+  JetArgs j;
+  j.W = (stage <= 1) ? ev.U : (stage == 2 ? ev.U1 : ev.U2);
+  j.D = ev.D;
+  j.s = ev.dev;
+  j.g = ev.g;
+  j.njet = ev.njet;
+  j.stage = stage;
+  j.deposit = ev.deposit;
+  j.t = batch_stage_time(ev, *b.step, stage);
+  j.dt = ev.dt;
+  j.eos_dof = ev.eos_dof;
+  j.hbarc = ev.hbarc;
+  jet_body<R>(j);
+}
+
+// FP64 conservation sums of every event (grid kSumBlocks x n_events, then n_events).
+template <class R>
+__global__ void __launch_bounds__(256) k_bsums_partial(BatchArgs<R> b) {
+  const BatchEvent& ev = b.ev[blockIdx.y];
+  sums_partial_body<R>(static_cast<const R*>(ev.U), ev.g.nc, ev.part, blockIdx.x, gridDim.x);
+}
+
+template <class R>
+__global__ void __launch_bounds__(256) k_bsums_final(BatchArgs<R> b) {
+  const BatchEvent& ev = b.ev[blockIdx.x];
+  sums_final_body(ev.part, kSumBlocks, ev.dV, ev.dev);
+}
+
+__global__ void k_bstep(long long* step) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *step = *step + 1;
 }
 
 // ---------------------------------------------------------------------------
@@ -589,8 +810,17 @@ void launch_tile_t(const StageArgs<R>& base, hipStream_t st) {
   hipLaunchKernelGGL((k_tile<R, S, AX, AX == 2>), grid, dim3(512), lds, st, a);
 }
 
+template <class R, int S>
+void launch_xtile_t(const StageArgs<R>& base, hipStream_t st) {
+  StageArgs<R> a = base;
+  a.inv_d = R(1.0 / a.g.dx[0]);
+  const size_t lds = (size_t)2 * 5 * kXTileP * kXTileY * sizeof(R);
+  dim3 grid((a.g.n[0] + kXTileX - 1) / kXTileX, (a.g.n[1] + kXTileY - 1) / kXTileY, a.g.n[2]);
+  hipLaunchKernelGGL((k_xtile<R, S>), grid, dim3(512), lds, st, a);
+}
+
 // kernel: 0 x-faces, 1 x boundary faces, 2 y-march, 3 z-march (+ combine),
-// 4 y-tile, 5 z-tile (+ combine)
+// 4 y-tile, 5 z-tile (+ combine), 6 x-tile (all x faces, boundary included)
 template <class R>
 hipError_t launch_face_kernel(int kernel, const StageArgs<R>& a, int scheme, int seg, hipStream_t st) {
 #define HYDRO_DISPATCH(S)                                  \
@@ -600,7 +830,8 @@ hipError_t launch_face_kernel(int kernel, const StageArgs<R>& a, int scheme, int
     case 2: launch_march_t<R, S, 1>(a, seg, st); break;    \
     case 3: launch_march_t<R, S, 2>(a, seg, st); break;    \
     case 4: launch_tile_t<R, S, 1>(a, st); break;          \
-    default: launch_tile_t<R, S, 2>(a, st); break;         \
+    case 5: launch_tile_t<R, S, 2>(a, st); break;          \
+    default: launch_xtile_t<R, S>(a, st); break;           \
   }
   if (scheme == kWenoJS) {
     HYDRO_DISPATCH(kWenoJS)
@@ -641,7 +872,55 @@ hipError_t launch_primitives(const R* U, R* prim, long long nc, double g, double
   return hipGetLastError();
 }
 
+// Items per axis of one event (tiles of the batched kernels).
+long long batch_items(int AX, const Grid& g) {
+  if (AX == 0)
+    return (long long)((g.n[0] + kXTileX - 1) / kXTileX) * ((g.n[1] + kXTileY - 1) / kXTileY) * g.n[2];
+  const int no = AX == 1 ? g.n[2] : g.n[1];
+  return (long long)((g.n[0] + kTileX - 1) / kTileX) * ((g.n[AX] + kTileA - 1) / kTileA) * no;
+}
+
+// blocks: workgroups of the axis kernel (0: one per item).
+template <class R>
+hipError_t launch_batch_axis(int AX, const BatchArgs<R>& b, int scheme, long long blocks, hipStream_t st) {
+  const long long nb = (blocks <= 0 || blocks > b.items) ? b.items : blocks;
+  if (nb <= 0) return hipSuccess;
+  const size_t lds = (size_t)2 * 5 * 40 * 16 * sizeof(R);  // kXTileP*kXTileY == kTileP*kTileXP
+  static_assert(kXTileP * kXTileY == kTileP * kTileXP, "tile LDS sizes");
+  const dim3 grid((unsigned)nb), tb(512);
+#define HYDRO_BAXIS(S)                                                                  \
+  if (AX == 0) hipLaunchKernelGGL((k_btile<R, S, 0>), grid, tb, lds, st, b);            \
+  else if (AX == 1) hipLaunchKernelGGL((k_btile<R, S, 1>), grid, tb, lds, st, b);       \
+  else hipLaunchKernelGGL((k_btile<R, S, 2>), grid, tb, lds, st, b);
+  if (scheme == kWenoJS) {
+    HYDRO_BAXIS(kWenoJS)
+  } else if (scheme == kWenoLinear) {
+    HYDRO_BAXIS(kWenoLinear)
+  } else {
+    HYDRO_BAXIS(kWenoZ)
+  }
+#undef HYDRO_BAXIS
+  return hipGetLastError();
+}
+
+template <class R>
+hipError_t launch_batch_jet(const BatchArgs<R>& b, hipStream_t st) {
+  hipLaunchKernelGGL((k_bjet<R>), dim3(b.n_events), dim3(512), 0, st, b);
+  return hipGetLastError();
+}
+
+template <class R>
+hipError_t launch_batch_sums(const BatchArgs<R>& b, long long* step, hipStream_t st) {
+  hipLaunchKernelGGL((k_bsums_partial<R>), dim3(kSumBlocks, b.n_events), dim3(256), 0, st, b);
+  hipLaunchKernelGGL((k_bsums_final<R>), dim3(b.n_events), dim3(256), 0, st, b);
+  if (step) hipLaunchKernelGGL(k_bstep, dim3(1), dim3(64), 0, st, step);
+  return hipGetLastError();
+}
+
 #define HYDRO_INSTANTIATE(R)                                                                          \
+  template hipError_t launch_batch_axis<R>(int, const BatchArgs<R>&, int, long long, hipStream_t);      \
+  template hipError_t launch_batch_jet<R>(const BatchArgs<R>&, hipStream_t);                          \
+  template hipError_t launch_batch_sums<R>(const BatchArgs<R>&, long long*, hipStream_t);              \
   template hipError_t launch_face_kernel<R>(int, const StageArgs<R>&, int, int, hipStream_t);          \
   template hipError_t launch_jet<R>(const JetArgs&, hipStream_t);                                     \
   template hipError_t launch_sums<R>(const R*, long long, double, double*, DevScalars*, hipStream_t); \

@@ -26,9 +26,13 @@ EXPORTED = [
     "hydro_primitives", "hydro_rhs", "hydro_sums", "hydro_get_state", "hydro_set_state", "hydro_diag",
     "hydro_last_error", "hydro_destroy", "hydro_profile", "hydro_profile_read", "hydro_set_option",
     "hydro_get_option", "hydro_reset", "hydro_set_jet", "hydro_loss_eps2", "hydro_adjoint_step",
-    "hydro_init_vjp",
+    "hydro_init_vjp", "hydro_batch_workspace_bytes", "hydro_batch_create", "hydro_batch_add_jet", "hydro_batch_run",
+    "hydro_batch_rhs", "hydro_batch_set_option", "hydro_batch_get_option", "hydro_batch_autotune",
+    "hydro_batch_sums", "hydro_batch_get_state", "hydro_batch_diag", "hydro_batch_last_error",
+    "hydro_batch_destroy",
 ]
-OPT_YZ_KERNEL, OPT_MARCH_SEG = 0, 1
+OPT_YZ_KERNEL, OPT_MARCH_SEG, OPT_X_KERNEL = 0, 1, 2
+BOPT_BLOCKS_X, BOPT_BLOCKS_Y, BOPT_BLOCKS_Z, BOPT_GRAPH = 0, 1, 2, 3
 KERNELS = ["xface", "xbound", "ymarch", "jet", "zmarch", "sums", "adjoint"]
 
 
@@ -106,6 +110,27 @@ def load_library(path: str = LIB_PATH):
     lib.hydro_init_vjp.argtypes = [vp, vp, vp, vp, vp]
     lib.hydro_get_option.argtypes = [vp, ctypes.c_int, ctypes.POINTER(ctypes.c_int)]
     lib.hydro_profile_read.argtypes = [vp, dp, ctypes.POINTER(ctypes.c_int64), ctypes.c_int]
+    lib.hydro_batch_workspace_bytes.argtypes = [cp, ctypes.c_int]
+    lib.hydro_batch_workspace_bytes.restype = ctypes.c_size_t
+    lib.hydro_batch_create.argtypes = [cp, ctypes.c_int, ctypes.POINTER(vp), ctypes.POINTER(vp), vp, ctypes.c_size_t,
+                                       vp, ctypes.POINTER(vp)]
+    lib.hydro_batch_add_jet.argtypes = [vp, ctypes.c_int, ctypes.POINTER(JetC), ctypes.POINTER(ctypes.c_int)]
+    lib.hydro_batch_run.argtypes = [vp, ctypes.c_int, vp]
+    lib.hydro_batch_rhs.argtypes = [vp, vp]
+    lib.hydro_batch_set_option.argtypes = [vp, ctypes.c_int, ctypes.c_longlong]
+    lib.hydro_batch_get_option.argtypes = [vp, ctypes.c_int, ctypes.POINTER(ctypes.c_longlong)]
+    lib.hydro_batch_autotune.argtypes = [vp, ctypes.c_char_p, vp, ctypes.POINTER(ctypes.c_int)]
+    lib.hydro_batch_sums.argtypes = [vp, ctypes.c_int, dp]
+    lib.hydro_batch_get_state.argtypes = [vp, ctypes.c_int, dp, ctypes.POINTER(ctypes.c_int64), dp, ctypes.c_int]
+    lib.hydro_batch_diag.argtypes = [vp, ctypes.POINTER(ctypes.c_int64)]
+    lib.hydro_batch_last_error.argtypes = [vp]
+    lib.hydro_batch_last_error.restype = ctypes.c_char_p
+    lib.hydro_batch_destroy.argtypes = [vp]
+    lib.hydro_batch_destroy.restype = None
+    for name in ("hydro_batch_create", "hydro_batch_add_jet", "hydro_batch_run", "hydro_batch_rhs",
+                 "hydro_batch_set_option", "hydro_batch_get_option", "hydro_batch_autotune", "hydro_batch_sums",
+                 "hydro_batch_get_state", "hydro_batch_diag"):
+        getattr(lib, name).restype = ctypes.c_int
     for name in ("hydro_init", "hydro_add_jet", "hydro_rk3_step", "hydro_primitives", "hydro_rhs", "hydro_sums",
                  "hydro_get_state", "hydro_set_state", "hydro_diag", "hydro_profile", "hydro_profile_read",
                  "hydro_set_option", "hydro_get_option", "hydro_reset", "hydro_set_jet", "hydro_loss_eps2",
@@ -337,3 +362,125 @@ def from_workload(w, precision: str = "f64", weno: str = "z", bc=None, adjoint_k
     for j in w.jets:
         h.add_jet(j.x0, j.dir, j.E0, j.t_start, j.kappa_rad, j.kappa_coll, j.cr_over_cf)
     return h
+
+
+class Batch:
+    """Events advanced together by the batch API (include/hydro.h): cfgs a
+    list of Config (shared precision and scheme), prims a list of FP64
+    primitive arrays (numpy or torch, (5, nz, ny, nx)) or None.  U[e] are
+    the events' conserved fields (torch, [5, nz, ny, nx])."""
+
+    def __init__(self, cfgs, prims=None, device: str = "cuda"):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("libhydro needs a GPU (torch.cuda.is_available() is False)")
+        self.lib = load_library()
+        n = len(cfgs)
+        self.n = n
+        self.cfgs = (Config * n)(*cfgs)
+        self.device = torch.device(device)
+        self.dtype = torch.float32 if cfgs[0].precision == F32 else torch.float64
+        self.shapes = [(c.n[2], c.n[1], c.n[0]) for c in cfgs]
+        self.U = [torch.empty((5,) + sh, dtype=self.dtype, device=self.device) for sh in self.shapes]
+        nbytes = int(self.lib.hydro_batch_workspace_bytes(self.cfgs, n))
+        if nbytes == 0:
+            raise HydroError(HYDRO_EINVAL, "invalid or incompatible batch configurations")
+        self.ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+        ws_ptr = self.ws.data_ptr() + (-self.ws.data_ptr()) % 256
+        self._keep = []
+        pp = None
+        if prims is not None:
+            ptrs = []
+            for e, p in enumerate(prims):
+                if p is None:
+                    ptrs.append(None)
+                    continue
+                if isinstance(p, np.ndarray):
+                    a = np.ascontiguousarray(p, dtype=np.float64)
+                    ptr = a.ctypes.data
+                else:
+                    a = p.to(dtype=torch.float64).contiguous()
+                    ptr = a.data_ptr()
+                assert tuple(a.shape) == (5,) + self.shapes[e], (a.shape, self.shapes[e])
+                self._keep.append(a)
+                ptrs.append(ptr)
+            pp = (ctypes.c_void_p * n)(*ptrs)
+        Up = (ctypes.c_void_p * n)(*[u.data_ptr() for u in self.U])
+        h = ctypes.c_void_p()
+        rc = self.lib.hydro_batch_create(self.cfgs, n, pp, Up, ws_ptr, nbytes, _stream_handle(), ctypes.byref(h))
+        if rc != HYDRO_OK:
+            raise HydroError(rc, self.lib.hydro_batch_last_error(None).decode())
+        self.b = h
+        self.njet = [0] * n
+
+    def _check(self, rc):
+        if rc != HYDRO_OK:
+            raise HydroError(rc, self.lib.hydro_batch_last_error(self.b).decode())
+
+    def add_jet(self, event: int, x0, dir=(1.0, 0.0, 0.0), E0=50.0, t_start=1.0, kappa_rad=4.0, kappa_coll=2.5,
+                cr_over_cf=1.0) -> int:
+        j = Hydro._jet(x0, dir, E0, t_start, kappa_rad, kappa_coll, cr_over_cf)
+        jid = ctypes.c_int(-1)
+        self._check(self.lib.hydro_batch_add_jet(self.b, int(event), ctypes.byref(j), ctypes.byref(jid)))
+        self.njet[event] += 1
+        return jid.value
+
+    def run(self, nsteps: int = 1, stream=None):
+        self._check(self.lib.hydro_batch_run(self.b, int(nsteps), _stream_handle(stream)))
+
+    def rhs(self, stream=None):
+        self._check(self.lib.hydro_batch_rhs(self.b, _stream_handle(stream)))
+
+    def autotune(self, cache_path: Optional[str] = None, stream=None) -> bool:
+        """Pick the workgroup counts; True if they came from the cache."""
+        fc = ctypes.c_int(0)
+        path = cache_path.encode() if cache_path else None
+        self._check(self.lib.hydro_batch_autotune(self.b, path, _stream_handle(stream), ctypes.byref(fc)))
+        return bool(fc.value)
+
+    def set_option(self, option: int, value: int):
+        self._check(self.lib.hydro_batch_set_option(self.b, int(option), int(value)))
+
+    def get_option(self, option: int) -> int:
+        v = ctypes.c_longlong(0)
+        self._check(self.lib.hydro_batch_get_option(self.b, int(option), ctypes.byref(v)))
+        return v.value
+
+    def sums(self, event: int) -> np.ndarray:
+        out = (ctypes.c_double * 6)()
+        self._check(self.lib.hydro_batch_sums(self.b, int(event), out))
+        return np.array(list(out))
+
+    def get_state(self, event: int):
+        t = ctypes.c_double(0)
+        st = ctypes.c_int64(0)
+        nj = self.njet[event]
+        E = (ctypes.c_double * max(1, nj))()
+        self._check(self.lib.hydro_batch_get_state(self.b, int(event), ctypes.byref(t), ctypes.byref(st), E, nj))
+        return t.value, st.value, np.array(list(E)[:nj])
+
+    def fixups(self) -> int:
+        f = ctypes.c_int64(0)
+        self._check(self.lib.hydro_batch_diag(self.b, ctypes.byref(f)))
+        return f.value
+
+    def close(self):
+        if getattr(self, "b", None):
+            self.lib.hydro_batch_destroy(self.b)
+            self.b = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def batch_from_workloads(ws, precision: str = "f32", weno: str = "z", device="cuda") -> Batch:
+    """Batch of workloads.Workload events, with their jets."""
+    cfgs = [make_config(w.n, w.dx, w.dt, w.t0, w.bc, precision, weno, w.deposit) for w in ws]
+    b = Batch(cfgs, [w.prim0 for w in ws], device=device)
+    for e, w in enumerate(ws):
+        for j in w.jets:
+            b.add_jet(e, j.x0, j.dir, j.E0, j.t_start, j.kappa_rad, j.kappa_coll, j.cr_over_cf)
+    return b

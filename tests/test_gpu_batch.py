@@ -1,0 +1,188 @@
+"""GPU batches: an ensemble advanced by the batch API (persistent tile
+launches over every event, graph replay) against the same events advanced
+one by one with hydro_rk3_step, against the oracle, and across launch shapes.
+
+Every face of a batched event is computed by the same device code and
+arithmetic as in the single-event path, so the bar is bitwise equality of the
+states, sums, ledgers and jet energies; the oracle bar is the FP64 1e-12 of
+the single-event parity tests.
+"""
+import os
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_1511_02137_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def need_gpu():
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a GPU")
+    from paper_1511_02137_amd import hydro as H
+    H.load_library()
+
+
+def H():
+    from paper_1511_02137_amd import hydro
+    return hydro
+
+
+def small_ensemble(n_events=7, seed=11, steps=4):
+    """Uneven small events: edges not multiples of the tile sizes, a periodic
+    axis here and there, Gaussian and NGP deposits, 0-3 jets."""
+    ws = W.ensemble(seed=seed, n_events=n_events, edges=(12, 20, 33, 40), steps=steps)
+    rng = np.random.default_rng(seed)
+    for k, w in enumerate(ws):
+        if k % 3 == 1:
+            w.bc = ("periodic", "outflow", "periodic")
+        if k % 2 == 1:
+            w.deposit = "gauss"
+        for j in w.jets:  # keep the jets inside these small boxes
+            j.x0 = tuple(float(rng.uniform(-0.2, 0.2) * w.n[d] * w.dx[d]) for d in range(3))
+    return ws
+
+
+def run_single(w, steps, precision):
+    h = H().from_workload(w, precision=precision)
+    h.step(steps)
+    torch.cuda.synchronize()
+    out = (h.U.cpu().numpy(), h.sums(), h.get_state()[2])
+    h.close()
+    return out
+
+
+def assert_batch_equals_single(b, ws, steps, precision):
+    for e, w in enumerate(ws):
+        U, sums, Ej = run_single(w, steps, precision)
+        assert np.array_equal(b.U[e].cpu().numpy(), U), ("event", e, w.n)
+        assert np.array_equal(b.sums(e), sums), ("sums", e)
+        assert np.array_equal(b.get_state(e)[2], Ej), ("E_jet", e)
+
+
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+def test_batch_matches_single_events_bitwise(precision):
+    ws = small_ensemble()
+    print("batch events", [w.n for w in ws], flush=True)
+    b = H().batch_from_workloads(ws, precision=precision)
+    b.run(4)
+    torch.cuda.synchronize()
+    assert_batch_equals_single(b, ws, 4, precision)
+    assert b.get_state(0)[1] == 4
+    b.close()
+
+
+def test_batch_event_matches_oracle():
+    ws = small_ensemble(n_events=3, seed=5)
+    b = H().batch_from_workloads(ws, precision="f64")
+    b.run(3)
+    torch.cuda.synchronize()
+    for e, w in enumerate(ws):
+        pb = O.Problem(n=w.n, dx=w.dx, t0=w.t0, dt=w.dt, bc=tuple(w.bc), deposit=w.deposit)
+        st = O.run(pb, O.prim_to_cons(pb, w.prim0), 3, [O.Jet(**j.__dict__) for j in w.jets])
+        got = b.U[e].cpu().numpy()
+        scale = np.abs(st.U[0]).max()
+        err = np.abs(got - st.U).max() / scale
+        assert err <= 1e-12, (e, w.n, err)
+    b.close()
+
+
+def test_launch_shapes_and_graph_do_not_change_results():
+    ws = small_ensemble(n_events=5, seed=3)
+    ref = H().batch_from_workloads(ws, precision="f64")
+    ref.set_option(H().BOPT_GRAPH, 0)
+    for a in (H().BOPT_BLOCKS_X, H().BOPT_BLOCKS_Y, H().BOPT_BLOCKS_Z):
+        ref.set_option(a, 0)  # one workgroup per tile
+    shapes = [(1, 1, 1), (7, 3, 5), (256, 512, 1024)]
+    others = []
+    for sh in shapes:
+        b = H().batch_from_workloads(ws, precision="f64")
+        for a, v in zip((H().BOPT_BLOCKS_X, H().BOPT_BLOCKS_Y, H().BOPT_BLOCKS_Z), sh):
+            b.set_option(a, v)
+        others.append(b)
+    # graph replays interleaved with eager work and synchronisation, each compared
+    for _ in range(3):
+        ref.run(1)
+        torch.cuda.synchronize()
+        want = [u.cpu().numpy() for u in ref.U]
+        for b in others:
+            b.run(1)
+            torch.cuda.synchronize()
+            for e in range(len(ws)):
+                assert np.array_equal(b.U[e].cpu().numpy(), want[e])
+    for b in others + [ref]:
+        b.close()
+
+
+def test_autotune_cache_and_bitwise_results(tmp_path):
+    ws = small_ensemble(n_events=4, seed=8)
+    cache = str(tmp_path / "tune.txt")
+    b = H().batch_from_workloads(ws, precision="f32")
+    assert b.autotune(cache) is False
+    picks = [b.get_option(a) for a in (0, 1, 2)]
+    assert os.path.exists(cache) and len(open(cache).read().split()) == 4
+    b2 = H().batch_from_workloads(ws, precision="f32")
+    assert b2.autotune(cache) is True
+    assert [b2.get_option(a) for a in (0, 1, 2)] == picks
+    b.run(3)
+    torch.cuda.synchronize()
+    assert_batch_equals_single(b, ws, 3, "f32")
+    b.close()
+    b2.close()
+
+
+def test_rhs_form_changes_no_state():
+    ws = small_ensemble(n_events=3, seed=2)
+    b = H().batch_from_workloads(ws, precision="f64")
+    before = [u.clone() for u in b.U]
+    b.rhs()
+    b.run(1)
+    torch.cuda.synchronize()
+    c = H().batch_from_workloads(ws, precision="f64")
+    c.run(1)
+    torch.cuda.synchronize()
+    for e in range(3):
+        assert np.array_equal(b.U[e].cpu().numpy(), c.U[e].cpu().numpy())
+    del before
+    b.close()
+    c.close()
+
+
+def test_batch_rejects_incompatible_events():
+    cfgs = [H().make_config((16, 16, 16), precision="f64"), H().make_config((16, 16, 16), precision="f32")]
+    with pytest.raises(H().HydroError):
+        H().Batch(cfgs, None)
+
+
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+def test_single_event_x_tile_matches_row_kernel(precision):
+    w = W.small_event(n=(37, 21, 18))
+    w.jets[0].x0 = (-0.5, 0.1, 0.05)
+    outs = []
+    for xk in (0, 1):
+        for bc in (None, ("periodic", "periodic", "outflow")):
+            h = H().from_workload(w, precision=precision, bc=bc)
+            h.set_option(H().OPT_X_KERNEL, xk)
+            h.step(3)
+            torch.cuda.synchronize()
+            outs.append(h.U.cpu().numpy())
+            h.close()
+    assert np.array_equal(outs[0], outs[2]) and np.array_equal(outs[1], outs[3])
+
+
+def test_full_ensemble_matches_single_events():
+    """The 64-event ensemble (edges 64/96/128, 0-3 jets, FP32) for 2 steps,
+    every event bitwise equal to its own single-event run."""
+    ws = W.ensemble(steps=2)
+    b = H().batch_from_workloads(ws, precision="f32")
+    b.autotune(None)
+    b.run(2)
+    torch.cuda.synchronize()
+    assert_batch_equals_single(b, ws, 2, "f32")
+    assert b.fixups() == 0
+    b.close()
