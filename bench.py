@@ -172,6 +172,7 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target length of the CPU oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--yz", choices=["tile", "march"], default="tile", help="y/z face kernels")
+    ap.add_argument("--x", choices=["row", "tile"], default="row", help="x face kernel")
     ap.add_argument("--adjoint-n", type=int, default=128, help="grid edge of the differentiable run (0: skip)")
     ap.add_argument("--adjoint-steps", type=int, default=100)
     ap.add_argument("--adjoint-ckpt", type=int, default=10)
@@ -205,6 +206,7 @@ def main():
     w = W.paper_event(2, n=(args.n,) * 3)
     h = H.from_workload(w, precision=args.precision)
     h.set_option(H.OPT_YZ_KERNEL, 0 if args.yz == "tile" else 1)
+    h.set_option(H.OPT_X_KERNEL, 0 if args.x == "row" else 1)
     nc = w.n[0] * w.n[1] * w.n[2]
 
     h.step(args.warmup)
@@ -257,7 +259,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": "%s: %d^3 cells, dx 0.1 fm, dt 0.02 fm/c, p = e/3, WENO7-Z + LF split, "
                                "SSP-RK3, 1 jet (NGP), outflow" % (w.name, args.n),
-                   "grid": list(w.n), "precision": args.precision, "jets": len(w.jets), "yz_kernel": args.yz},
+                   "grid": list(w.n), "precision": args.precision, "jets": len(w.jets), "yz_kernel": args.yz,
+                   "x_kernel": args.x},
         "roofline": roofline,
         "step_alu_frac": step_frac,
         "flops_per_cell_update": FLOPS_PER_CELL_UPDATE,

@@ -53,11 +53,11 @@ __device__ __forceinline__ PrimV c2p(double E, double Mx, double My, double Mz, 
     M2 = Mx * Mx + My * My + Mz * Mz;
   }
   const double e = 3.0 * (E * E - M2) / (E + sqrt(4.0 * E * E - 3.0 * M2));
-  const double W = E + e / 3.0;
+  const double iW = 1.0 / (E + e * (1.0 / 3.0));
   r.e = e;
-  r.v[0] = Mx / W;
-  r.v[1] = My / W;
-  r.v[2] = Mz / W;
+  r.v[0] = Mx * iW;
+  r.v[1] = My * iW;
+  r.v[2] = Mz * iW;
   return r;
 }
 
@@ -71,7 +71,7 @@ __device__ __forceinline__ PrimV c2p(const R u[5], unsigned& fix) {
 template <class R, int AX>
 __device__ __forceinline__ void split_flux(const R u[5], const PrimV& p, R Fp[5], R Fm[5]) {
   const R vd = (R)p.v[AX];
-  const R pr = (R)(p.e / 3.0);
+  const R pr = (R)(p.e * (1.0 / 3.0));
   R f[5];
   f[0] = u[1 + AX];
   f[1] = (AX == 0) ? u[1] * vd + pr : u[1] * vd;

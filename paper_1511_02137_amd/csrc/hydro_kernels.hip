@@ -216,19 +216,22 @@ __global__ void __launch_bounds__(256) k_march(StageArgs<R> a) {
 
 // ---------------------------------------------------------------------------
 // y- or z-faces from an LDS tile (AX = 1 or 2).  A workgroup of 512 lanes
-// owns 16 cells along x (coalesced 128-byte rows) by 32 cells along AX at one
-// value of the remaining axis.  It stores the split AX-fluxes of its 16 x 40
-// points (4 ghost rows on each side) in LDS, reconstructs the 33 face rows
-// (one face per lane, one extra row for 16 lanes) and forms the divergence.
+// owns 16 cells along x (coalesced 128-byte rows) by 31 cells along AX at one
+// value of the remaining axis, so that its 32 face rows are exactly one face
+// per lane.  It stores the split AX-fluxes of its 16 x 39 points (4 ghost rows
+// on each side) in LDS, reconstructs the face rows and forms the divergence;
+// each lane's D is loaded before the reconstructions to hide its latency.
 // LAST (z): adds D, does the RK combine with the cell's own stage input kept
 // in registers from the load, and writes the stage output.
 constexpr int kTileX = 16;
-constexpr int kTileA = 32;
-constexpr int kTileP = kTileA + 8;   // points along AX
 constexpr int kTileXP = kTileX;      // x pitch of the LDS arrays (128-byte rows)
 
-template <class R, int S, int AX, bool LAST>
+// Tile length along the axis: 31 cells (32 face rows, one face per lane)
+// or 32 cells (33 face rows, the last one by 16 lanes); the launchers pick
+// the one that wastes less for the axis length (tile_len).
+template <class R, int S, int AX, bool LAST, int kTileA>
 __device__ __forceinline__ void tile_body(const StageArgs<R>& a, int bx, int by, int bz, R* s) {
+  constexpr int kTileP = kTileA + 8;  // points along AX
   R* sFp = s;                              // [5][kTileP][kTileXP]
   R* sFm = s + 5 * kTileP * kTileXP;       // [5][kTileP][kTileXP]
   const int nx = a.g.n[0], ny = a.g.n[1];
@@ -236,7 +239,7 @@ __device__ __forceinline__ void tile_body(const StageArgs<R>& a, int bx, int by,
   const int bc = a.g.bc[AX];
   const long long nc = a.g.nc;
   const int tx = threadIdx.x & (kTileX - 1);
-  const int ta = threadIdx.x >> 4;  // 0..31
+  const int ta = threadIdx.x >> 4;  // 0..31: own cell a0 + ta (ta < kTileA), face row ta
   const int x = bx * kTileX + tx;
   const int a0 = by * kTileA;
   const int o = bz;
@@ -249,7 +252,7 @@ __device__ __forceinline__ void tile_body(const StageArgs<R>& a, int bx, int by,
   // pass 1: own cell (slot ta + 4)
   {
     const int p = a0 + ta;
-    if (xin) {
+    if (xin && ta < kTileA) {
       load5(a.W, nc, base + (long long)map_idx(p, n, bc) * stride, own);
       const PrimV pv = c2p(own, fix);
       R Fp[5], Fm[5];
@@ -259,6 +262,18 @@ __device__ __forceinline__ void tile_body(const StageArgs<R>& a, int bx, int by,
         sFp[(c * kTileP + ta + 4) * kTileXP + tx] = Fp[c];
         sFm[(c * kTileP + ta + 4) * kTileXP + tx] = Fm[c];
       }
+    }
+  }
+  // the own cell's D, loaded early so that its latency overlaps the ghost
+  // rows and the reconstructions
+  const int ac = a0 + ta;
+  const bool own_ok = xin && ta < kTileA && ac < n;
+  const long long cell = base + (long long)ac * stride;
+  R dpre[5];
+  if (own_ok) {
+#pragma unroll
+    for (int c = 0; c < 5; ++c) {
+      dpre[c] = a.D[c * nc + cell];
     }
   }
   // pass 2: 4 ghost rows on each side (128 lanes)
@@ -281,11 +296,11 @@ __device__ __forceinline__ void tile_body(const StageArgs<R>& a, int bx, int by,
   }
   __syncthreads();
 
-  // faces f = 0..32: face (a0 - 1 + f) + 1/2; F+ at slots f..f+6, F- at f+1..f+7
+  // face rows f = 0..kTileA: face (a0 - 1 + f) + 1/2; F+ at slots f..f+6, F- at f+1..f+7
   const int nf = min(kTileA, n - a0) + 1;  // face rows this tile needs
   R Fh[5], Fh2[5];
   const bool has1 = xin && ta < nf;
-  const bool has2 = xin && threadIdx.x < kTileX && kTileA < nf;
+  const bool has2 = (kTileA + 1) * kTileX > 512 && xin && threadIdx.x < kTileX && kTileA < nf;
   if (has1) {
 #pragma unroll
     for (int c = 0; c < 5; ++c) {
@@ -320,17 +335,15 @@ __device__ __forceinline__ void tile_body(const StageArgs<R>& a, int bx, int by,
   }
   __syncthreads();
 
-  const int ac = a0 + ta;
-  if (xin && ac < n) {
-    const long long cell = base + (long long)ac * stride;
+  if (own_ok) {
 #pragma unroll
     for (int c = 0; c < 5; ++c) {
       const R div = (sF[(c * (kTileA + 1) + ta) * kTileXP + tx] - sF[(c * (kTileA + 1) + ta + 1) * kTileXP + tx]) * a.inv_d;
       R* d = a.D + c * nc + cell;
       if (!LAST) {
-        *d = *d + div;
+        *d = dpre[c] + div;
       } else {
-        const R L = *d + div;
+        const R L = dpre[c] + div;
         const R w = own[c];
         R outv;
         if (a.stage == 0) {
@@ -350,27 +363,27 @@ __device__ __forceinline__ void tile_body(const StageArgs<R>& a, int bx, int by,
 }
 
 
-template <class R, int S, int AX, bool LAST>
+template <class R, int S, int AX, bool LAST, int A>
 __global__ void __launch_bounds__(512) k_tile(StageArgs<R> a) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  tile_body<R, S, AX, LAST>(a, blockIdx.x, blockIdx.y, blockIdx.z, reinterpret_cast<R*>(smem_raw));
+  tile_body<R, S, AX, LAST, A>(a, blockIdx.x, blockIdx.y, blockIdx.z, reinterpret_cast<R*>(smem_raw));
 }
 
 // ---------------------------------------------------------------------------
-// x-faces from an LDS tile: a workgroup of 512 lanes owns 32 cells along x by
-// 16 rows along y at one z.  The 40 x 16 points (4 ghosts on each side) are
-// loaded x-fastest (coalesced) and their split x-fluxes stored [c][x][y], so a
-// face lane (y fastest) reads them without bank conflicts; the 33 face rows
-// are reconstructed (one face per lane, one extra row for 16 lanes) and the
-// divergence is formed with lanes x-fastest again and assigned to D (x is the
-// first axis).  Same per-face arithmetic as k_xface + k_xbound.
-constexpr int kXTileX = 32;
+// x-faces from an LDS tile: a workgroup of 512 lanes owns 31 or 32 cells
+// along x (tile_len) by 16 rows along y at one z.  The (A + 8) x 16 points
+// (4 ghosts on each side) are loaded x-fastest (coalesced) and their split
+// x-fluxes stored [c][x][y], so a face lane (y fastest) reads them without
+// bank conflicts; the A + 1 face rows are reconstructed (one face per lane;
+// for A = 32 one extra row by 16 lanes) and the divergence is formed with
+// lanes x-fastest again and assigned to D (x is the first axis).  Same
+// per-face arithmetic as k_xface + k_xbound.
 constexpr int kXTileY = 16;
-constexpr int kXTileP = kXTileX + 8;
 constexpr int kXFacePitch = kXTileY + 1;
 
-template <class R, int S>
+template <class R, int S, int kXTileX>
 __device__ __forceinline__ void xtile_body(const StageArgs<R>& a, int bx, int by, int bz, R* s) {
+  constexpr int kXTileP = kXTileX + 8;
   R* sFp = s;                                // [5][kXTileP][kXTileY]
   R* sFm = s + 5 * kXTileP * kXTileY;        // [5][kXTileP][kXTileY]
   const int nx = a.g.n[0], ny = a.g.n[1];
@@ -399,11 +412,11 @@ __device__ __forceinline__ void xtile_body(const StageArgs<R>& a, int bx, int by
 
   // faces f = 0..32: face (x0 - 1 + f) + 1/2; F+ at slots f..f+6, F- at f+1..f+7
   const int r = threadIdx.x & (kXTileY - 1);
-  const int f = threadIdx.x >> 4;  // 0..31
+  const int f = threadIdx.x >> 4;  // 0..31: face row f
   const int nf = min(kXTileX, nx - x0) + 1;
   const bool yin = y0 + r < ny;
   const bool has1 = yin && f < nf;
-  const bool has2 = yin && threadIdx.x < kXTileY && kXTileX < nf;
+  const bool has2 = (kXTileX + 1) * kXTileY > 512 && yin && threadIdx.x < kXTileY && kXTileX < nf;
   R Fh[5], Fh2[5];
   if (has1) {
 #pragma unroll
@@ -439,8 +452,8 @@ __device__ __forceinline__ void xtile_body(const StageArgs<R>& a, int bx, int by
   }
   __syncthreads();
 
-  const int xa = threadIdx.x & (kXTileX - 1), ra = threadIdx.x >> 5;
-  if (x0 + xa < nx && y0 + ra < ny) {
+  const int xa = threadIdx.x & 31, ra = threadIdx.x >> 5;
+  if (xa < kXTileX && x0 + xa < nx && y0 + ra < ny) {
     const long long cell = zbase + (long long)(y0 + ra) * nx + x0 + xa;
 #pragma unroll
     for (int c = 0; c < 5; ++c) {
@@ -452,10 +465,10 @@ __device__ __forceinline__ void xtile_body(const StageArgs<R>& a, int bx, int by
   add_fixups(a.fixups, fix);
 }
 
-template <class R, int S>
+template <class R, int S, int A>
 __global__ void __launch_bounds__(512) k_xtile(StageArgs<R> a) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  xtile_body<R, S>(a, blockIdx.x, blockIdx.y, blockIdx.z, reinterpret_cast<R*>(smem_raw));
+  xtile_body<R, S, A>(a, blockIdx.x, blockIdx.y, blockIdx.z, reinterpret_cast<R*>(smem_raw));
 }
 
 // ---------------------------------------------------------------------------
@@ -711,13 +724,17 @@ __global__ void __launch_bounds__(512) k_btile(BatchArgs<R> b) {
     const BatchEvent& ev = b.ev[e];
     const long long local = it - b.off[e];
     const StageArgs<R> a = batch_stage_args<R>(ev, b.stage, b.eps, AX);
+    const int A = tile_len(ev.g.n[AX]);
     if (AX == 0) {
-      const int gx = (ev.g.n[0] + kXTileX - 1) / kXTileX, gy = (ev.g.n[1] + kXTileY - 1) / kXTileY;
-      xtile_body<R, S>(a, (int)(local % gx), (int)((local / gx) % gy), (int)(local / ((long long)gx * gy)), s);
+      const int gx = (ev.g.n[0] + A - 1) / A, gy = (ev.g.n[1] + kXTileY - 1) / kXTileY;
+      const int bx = (int)(local % gx), by = (int)((local / gx) % gy), bz = (int)(local / ((long long)gx * gy));
+      if (A == 31) xtile_body<R, S, 31>(a, bx, by, bz, s);
+      else xtile_body<R, S, 32>(a, bx, by, bz, s);
     } else {
-      const int gx = (ev.g.n[0] + kTileX - 1) / kTileX, ga = (ev.g.n[AX] + kTileA - 1) / kTileA;
-      tile_body<R, S, AX, AX == 2>(a, (int)(local % gx), (int)((local / gx) % ga),
-                                   (int)(local / ((long long)gx * ga)), s);
+      const int gx = (ev.g.n[0] + kTileX - 1) / kTileX, ga = (ev.g.n[AX] + A - 1) / A;
+      const int bx = (int)(local % gx), by = (int)((local / gx) % ga), bz = (int)(local / ((long long)gx * ga));
+      if (A == 31) tile_body<R, S, AX, AX == 2, 31>(a, bx, by, bz, s);
+      else tile_body<R, S, AX, AX == 2, 32>(a, bx, by, bz, s);
     }
     __syncthreads();  // the next item overwrites the LDS tile
   }
@@ -805,18 +822,22 @@ void launch_tile_t(const StageArgs<R>& base, hipStream_t st) {
   a.inv_d = R(1.0 / a.g.dx[AX]);
   const int n = a.g.n[AX];
   const int no = (AX == 1) ? a.g.n[2] : a.g.n[1];
-  const size_t lds = (size_t)2 * 5 * kTileP * kTileXP * sizeof(R);
-  dim3 grid((nx + kTileX - 1) / kTileX, (n + kTileA - 1) / kTileA, no);
-  hipLaunchKernelGGL((k_tile<R, S, AX, AX == 2>), grid, dim3(512), lds, st, a);
+  const int A = tile_len(n);
+  const size_t lds = (size_t)2 * 5 * (A + 8) * kTileXP * sizeof(R);
+  dim3 grid((nx + kTileX - 1) / kTileX, (n + A - 1) / A, no);
+  if (A == 31) hipLaunchKernelGGL((k_tile<R, S, AX, AX == 2, 31>), grid, dim3(512), lds, st, a);
+  else hipLaunchKernelGGL((k_tile<R, S, AX, AX == 2, 32>), grid, dim3(512), lds, st, a);
 }
 
 template <class R, int S>
 void launch_xtile_t(const StageArgs<R>& base, hipStream_t st) {
   StageArgs<R> a = base;
   a.inv_d = R(1.0 / a.g.dx[0]);
-  const size_t lds = (size_t)2 * 5 * kXTileP * kXTileY * sizeof(R);
-  dim3 grid((a.g.n[0] + kXTileX - 1) / kXTileX, (a.g.n[1] + kXTileY - 1) / kXTileY, a.g.n[2]);
-  hipLaunchKernelGGL((k_xtile<R, S>), grid, dim3(512), lds, st, a);
+  const int A = tile_len(a.g.n[0]);
+  const size_t lds = (size_t)2 * 5 * (A + 8) * kXTileY * sizeof(R);
+  dim3 grid((a.g.n[0] + A - 1) / A, (a.g.n[1] + kXTileY - 1) / kXTileY, a.g.n[2]);
+  if (A == 31) hipLaunchKernelGGL((k_xtile<R, S, 31>), grid, dim3(512), lds, st, a);
+  else hipLaunchKernelGGL((k_xtile<R, S, 32>), grid, dim3(512), lds, st, a);
 }
 
 // kernel: 0 x-faces, 1 x boundary faces, 2 y-march, 3 z-march (+ combine),
@@ -874,10 +895,10 @@ hipError_t launch_primitives(const R* U, R* prim, long long nc, double g, double
 
 // Items per axis of one event (tiles of the batched kernels).
 long long batch_items(int AX, const Grid& g) {
-  if (AX == 0)
-    return (long long)((g.n[0] + kXTileX - 1) / kXTileX) * ((g.n[1] + kXTileY - 1) / kXTileY) * g.n[2];
+  const int A = tile_len(g.n[AX]);
+  if (AX == 0) return (long long)((g.n[0] + A - 1) / A) * ((g.n[1] + kXTileY - 1) / kXTileY) * g.n[2];
   const int no = AX == 1 ? g.n[2] : g.n[1];
-  return (long long)((g.n[0] + kTileX - 1) / kTileX) * ((g.n[AX] + kTileA - 1) / kTileA) * no;
+  return (long long)((g.n[0] + kTileX - 1) / kTileX) * ((g.n[AX] + A - 1) / A) * no;
 }
 
 // blocks: workgroups of the axis kernel (0: one per item).
@@ -885,8 +906,8 @@ template <class R>
 hipError_t launch_batch_axis(int AX, const BatchArgs<R>& b, int scheme, long long blocks, hipStream_t st) {
   const long long nb = (blocks <= 0 || blocks > b.items) ? b.items : blocks;
   if (nb <= 0) return hipSuccess;
-  const size_t lds = (size_t)2 * 5 * 40 * 16 * sizeof(R);  // kXTileP*kXTileY == kTileP*kTileXP
-  static_assert(kXTileP * kXTileY == kTileP * kTileXP, "tile LDS sizes");
+  const size_t lds = (size_t)2 * 5 * (32 + 8) * 16 * sizeof(R);  // the largest tile (A = 32)
+  static_assert(kXTileY == 16 && kTileXP == 16, "tile LDS sizes");
   const dim3 grid((unsigned)nb), tb(512);
 #define HYDRO_BAXIS(S)                                                                  \
   if (AX == 0) hipLaunchKernelGGL((k_btile<R, S, 0>), grid, tb, lds, st, b);            \
