@@ -76,20 +76,59 @@ def cpu_baseline(w, target_s: float):
         O.run(pb, U, 1, jets)
         return time.perf_counter() - t
 
+    cores = O.threads()
     planes = min(nz, 8)
     t = run_slab(planes)
     if t < 0.5 * target_s and planes < nz:
         planes = min(nz, max(planes + 1, int(planes * target_s / max(t, 1e-3))))
         t = run_slab(planes)
     cells = w.n[0] * w.n[1] * planes
+    # the same on one core, on a thinner slab (about a tenth of the time budget)
+    O.set_threads(1)
+    p1 = max(1, min(planes, int(planes * 0.1 * target_s / max(t * cores, 1e-3))))
+    t1 = run_slab(p1)
+    O.set_threads(cores)
+    model = ""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
     return {
         "value": cells * 3 / t,
         "unit": "cell-updates/s",
-        "cores": O.threads(),
+        "cores": cores,
         "kind": "oracle",
         "sample": "one RK3 step (3 stages) of the central %dx%dx%d z-slab of the %s workload, outflow, "
                   "%.1f s wall" % (w.n[0], w.n[1], planes, w.name, t),
+        "single_core_value": w.n[0] * w.n[1] * p1 * 3 / t1,
+        "single_core_sample": "the central %dx%dx%d z-slab, one step, %.1f s wall" % (w.n[0], w.n[1], p1, t1),
+        "host_cpu": model, "host_logical_cpus": os.cpu_count(),
     }
+
+
+def precision_check(n: int, steps: int):
+    """FP32 form against the FP64 form of the same run (paper shape, one jet):
+    relative L2 of e and |v| after `steps` steps (primitives in FP64)."""
+    import torch
+    from paper_1511_02137_amd import hydro as H
+    from paper_1511_02137_amd import workloads as W
+    w = W.paper_event(2, n=(n,) * 3)
+    prims = {}
+    for prec in ("f64", "f32"):
+        h = H.from_workload(w, precision=prec)
+        h.step(steps)
+        p = h.primitives().double()
+        prims[prec] = (p[0], torch.sqrt(p[1] ** 2 + p[2] ** 2 + p[3] ** 2))
+        h.close()
+        del h
+    out = {"workload": "%s, %d steps, FP32 form against FP64" % (w.name, steps)}
+    for k, name in ((0, "e"), (1, "abs_v")):
+        a, b = prims["f32"][k], prims["f64"][k]
+        out["rel_l2_" + name] = float(torch.linalg.vector_norm(a - b) / torch.linalg.vector_norm(b))
+    return out
 
 
 def adjoint_ratio(precision: str, n: int, steps: int, ckpt: int, repeats: int = 3):
@@ -178,6 +217,8 @@ def main():
     ap.add_argument("--adjoint-ckpt", type=int, default=10)
     ap.add_argument("--adjoint-precision", choices=["f64", "f32"], default="f32")
     ap.add_argument("--batch-steps", type=int, default=50, help="steps of the ensemble run (0: skip)")
+    ap.add_argument("--precision-steps", type=int, default=10,
+                    help="steps of the FP32-against-FP64 check at the stage shape (0: skip)")
     ap.add_argument("--batch-precision", choices=["f64", "f32"], default="f32")
     ap.add_argument("--tune-cache", default=None, help="autotuner cache file of the ensemble run")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -214,13 +255,17 @@ def main():
 
     h.profile(True)
     start = torch.cuda.Event(enable_timing=True)
-    stop = torch.cuda.Event(enable_timing=True)
+    marks = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
     torch.cuda.synchronize()
     start.record()
-    h.step(args.steps)
-    stop.record()
+    for i in range(args.steps):
+        h.step(1)
+        marks[i].record()
     torch.cuda.synchronize()
-    ms = start.elapsed_time(stop)
+    ms = start.elapsed_time(marks[-1])
+    per_step = sorted([start.elapsed_time(marks[0])] +
+                      [marks[i - 1].elapsed_time(marks[i]) for i in range(1, args.steps)])
+    median_ms = per_step[len(per_step) // 2]
     prof = h.profile_read()
     h.profile(False)
     fix = h.fixups()
@@ -252,6 +297,8 @@ def main():
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": ms / args.steps,
+        "median_ms_per_step": median_ms,
+        "value_without_sums": nc * 3 * args.steps / ((ms - prof["sums"][0]) * 1e-3),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -269,8 +316,10 @@ def main():
     }
     print("timed %d steps: %.3f ms/step, %.3e cell-updates/s" % (args.steps, ms / args.steps, value),
           file=sys.stderr, flush=True)
+    h.close()
+    if args.precision_steps > 0:
+        out["precision_check"] = precision_check(args.n, args.precision_steps)
     if args.adjoint_n > 0:
-        h.close()
         out["adjoint"] = adjoint_ratio(args.adjoint_precision, args.adjoint_n, args.adjoint_steps, args.adjoint_ckpt)
         print("adjoint/forward %.2f" % out["adjoint"]["ratio"], file=sys.stderr, flush=True)
     if args.batch_steps > 0:

@@ -84,6 +84,8 @@ def _load():
     jp = ctypes.POINTER(OJet)
     lib.oracle_threads.argtypes = []
     lib.oracle_threads.restype = ctypes.c_int
+    lib.oracle_set_threads.argtypes = [ctypes.c_int]
+    lib.oracle_set_threads.restype = None
     lib.oracle_weno7.argtypes = [dp, ctypes.c_int, ctypes.c_double, ctypes.c_int]
     lib.oracle_weno7.restype = ctypes.c_double
     lib.oracle_prim_to_cons.argtypes = [cp, dp, dp]
@@ -177,6 +179,11 @@ def _jets(jets):
 def threads() -> int:
     """OpenMP threads the oracle runs on."""
     return int(_load().oracle_threads())
+
+
+def set_threads(n: int) -> None:
+    """Run later oracle calls on n OpenMP threads."""
+    _load().oracle_set_threads(int(n))
 
 
 def weno7(a, scheme: str = "z", eps: float = 1e-6, p: int = 2) -> float:

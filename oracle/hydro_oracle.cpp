@@ -597,6 +597,15 @@ int oracle_threads(void) {
 #endif
 }
 
+// Set the OpenMP thread count of later calls (timing on one core or all).
+void oracle_set_threads(int n) {
+#ifdef _OPENMP
+  if (n > 0) omp_set_num_threads(n);
+#else
+  (void)n;
+#endif
+}
+
 // WENO7 left-biased reconstruction of seven values (unit tests).
 double oracle_weno7(const double* a, int scheme, double eps, int p) {
   return weno7_left<double>(a, scheme, eps, p);
