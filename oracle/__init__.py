@@ -2,7 +2,8 @@
 
 A plain FP64 implementation (``hydro_oracle.cpp``) of the scheme the paper
 describes: Eq. (1) ideal hydrodynamics with a source, Eq. (2) point sources of
-jets, Eq. (3) energy loss, 7th-order WENO and third-order Runge-Kutta
+jets, Eq. (3) energy loss, 7th-order WENO (5th order as the alternative the
+paper also names) and third-order Runge-Kutta
 (section "Simulation setup"), EOS p = e/3 (Fig. 3 caption).  This module only
 marshals numpy arrays into that library through ctypes.
 
@@ -11,7 +12,7 @@ Only ``tests/``, ``__graft_entry__.smoke()`` and the ``cpu_baseline`` leg of
 with this directory.
 
 Parity status per function (pins in tests/test_oracle_*.py):
-  weno7            pinned (sympy derivation, polynomial exactness, order)
+  weno7, weno5     pinned (sympy derivation, polynomial exactness, order)
   cons_to_prim     pinned (round trip, quadratic identity)
   prim_to_cons     pinned (round trip)
   rhs / run        pinned (uniform state, mirror symmetry, conservation,
@@ -63,7 +64,7 @@ class OJet(ctypes.Structure):
     ]
 
 
-WENO = {"z": 0, "js": 1, "linear": 2}
+WENO = {"z": 0, "js": 1, "linear": 2, "z5": 3, "js5": 4, "linear5": 5}
 BC = {"outflow": 0, "periodic": 1}
 DEPOSIT = {"ngp": 0, "gauss": 1}
 
@@ -88,6 +89,8 @@ def _load():
     lib.oracle_set_threads.restype = None
     lib.oracle_weno7.argtypes = [dp, ctypes.c_int, ctypes.c_double, ctypes.c_int]
     lib.oracle_weno7.restype = ctypes.c_double
+    lib.oracle_weno5.argtypes = [dp, ctypes.c_int, ctypes.c_double, ctypes.c_int]
+    lib.oracle_weno5.restype = ctypes.c_double
     lib.oracle_prim_to_cons.argtypes = [cp, dp, dp]
     lib.oracle_cons_to_prim.argtypes = [cp, dp, dp, llp]
     lib.oracle_rhs.argtypes = [cp, jp, ctypes.c_int, ip, dp, ctypes.c_double, dp, dp, llp]
@@ -184,6 +187,13 @@ def threads() -> int:
 def set_threads(n: int) -> None:
     """Run later oracle calls on n OpenMP threads."""
     _load().oracle_set_threads(int(n))
+
+
+def weno5(a, scheme: str = "z", eps: float = 1e-6, p: int = 2) -> float:
+    """WENO5 value at x_{i+1/2} from a_{i-2}..a_{i+2}; scheme z, js or linear."""
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    assert a.shape == (5,)
+    return float(_load().oracle_weno5(_dp(a), WENO[scheme], eps, p))
 
 
 def weno7(a, scheme: str = "z", eps: float = 1e-6, p: int = 2) -> float:

@@ -248,6 +248,52 @@ S weno7_left(const S* a, int scheme, double eps, int pz) {
 }
 
 // ---------------------------------------------------------------------------
+// WENO5 reconstruction of the value at x_{i+1/2} from the left, given
+// a[0..4] = a_{i-2}..a_{i+2}: candidate values q_k of the three quadratics
+// with the stencil values as cell averages, ideal weights (1, 6, 3)/10,
+// Jiang-Shu smoothness indicators beta_k = sum_{l=1,2} int_{cell i}
+// (d^l p_k/dx^l)^2 dx, and WENO-Z (tau = |b0 - b2|), Jiang-Shu or linear
+// weights, with the same eps and exponent conventions as weno7_left.
+template <class S>
+S weno5_left(const S* a, int scheme, double eps, int pz) {
+  S q[3];
+  q[0] = (2.0 * a[0] - 7.0 * a[1] + 11.0 * a[2]) / 6.0;
+  q[1] = (-1.0 * a[1] + 5.0 * a[2] + 2.0 * a[3]) / 6.0;
+  q[2] = (2.0 * a[2] + 5.0 * a[3] - 1.0 * a[4]) / 6.0;
+  const double d[3] = {0.1, 0.6, 0.3};
+  if (scheme == 2) return d[0] * q[0] + d[1] * q[1] + d[2] * q[2];
+  // With p_k = c0 + c1 x + c2 x^2 about the centre of cell i the integral is
+  // c1^2 + 13/3 c2^2; from the stencil differences D1, D2:
+  //   c2 = D2/2,  c1 = D1 + h_k D2,  h = 3/2, 1/2, -1/2.
+  const double hk[3] = {1.5, 0.5, -0.5};
+  S b[3];
+  for (int k = 0; k < 3; ++k) {
+    const S* f = a + k;  // a_{i-2+k} .. a_{i+k}
+    S D1 = f[1] - f[0];
+    S D2 = (f[2] - f[1]) - D1;
+    S c2 = D2 / 2.0;
+    S c1 = D1 + hk[k] * D2;
+    b[k] = c1 * c1 + (13.0 / 3.0) * c2 * c2;
+  }
+  S alpha[3];
+  if (scheme == 1) {
+    for (int k = 0; k < 3; ++k) alpha[k] = d[k] / ((eps + b[k]) * (eps + b[k]));
+  } else {
+    S tau = aabs(b[0] - b[2]);
+    for (int k = 0; k < 3; ++k) {
+      S r = tau / (b[k] + eps);
+      S rp = S(1.0);
+      for (int m = 0; m < pz; ++m) rp = rp * r;
+      alpha[k] = d[k] * (1.0 + rp);
+    }
+  }
+  S sum = alpha[0] + alpha[1] + alpha[2];
+  S out = S(0.0);
+  for (int k = 0; k < 3; ++k) out = out + (alpha[k] / sum) * q[k];
+  return out;
+}
+
+// ---------------------------------------------------------------------------
 // Cell-centre coordinate of index i along an axis with n cells.
 inline double centre(int i, int n, double dx) { return (i - 0.5 * (n - 1)) * dx; }
 
@@ -362,6 +408,16 @@ struct Solver {
           // faces i+1/2 for i = -1..n-1 (Fh[i+1])
           for (int i = -1; i < n; ++i) {
             int P = i + 4;  // padded index of cell i
+            if (c.weno >= 3) {  // 5th order: three ghost cells are used
+              S left[5], right[5];
+              for (int m = 0; m < 5; ++m) {
+                left[m] = Fp[P - 2 + m];    // F+ at i-2..i+2
+                right[m] = Fm[P + 3 - m];   // F- at i+3..i-1 (mirrored stencil)
+              }
+              Fh[i + 1] = weno5_left(left, c.weno - 3, c.weno_eps, c.weno_p) +
+                          weno5_left(right, c.weno - 3, c.weno_eps, c.weno_p);
+              continue;
+            }
             S left[7], right[7];
             for (int m = 0; m < 7; ++m) {
               left[m] = Fp[P - 3 + m];    // F+ at i-3..i+3
@@ -580,7 +636,7 @@ bool valid(const ocfg* c) {
     if (c->n[d] < 1 || c->dx[d] <= 0.0) return false;
     if (c->bc[d] != 0 && c->bc[d] != 1) return false;
   }
-  if (c->weno < 0 || c->weno > 2 || c->deposit < 0 || c->deposit > 1 || c->weno_p < 1) return false;
+  if (c->weno < 0 || c->weno > 5 || c->deposit < 0 || c->deposit > 1 || c->weno_p < 1) return false;
   return c->dt > 0.0;
 }
 
@@ -604,6 +660,11 @@ void oracle_set_threads(int n) {
 #else
   (void)n;
 #endif
+}
+
+// WENO5 left-biased reconstruction of five values (unit tests).
+double oracle_weno5(const double* a, int scheme, double eps, int p) {
+  return weno5_left<double>(a, scheme, eps, p);
 }
 
 // WENO7 left-biased reconstruction of seven values (unit tests).

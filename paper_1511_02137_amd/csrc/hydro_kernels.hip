@@ -92,36 +92,58 @@ __global__ void __launch_bounds__(TB) k_xface(StageArgs<R> a) {
   add_fixups(a.fixups, fix);
 }
 
-// Right boundary face of every row (outflow x): points nx-4..nx+3.
+// Right boundary face of every row (outflow x): points nx-4..nx+3 (the last
+// four copies of cell nx-1).  A workgroup takes 32 rows: one lane per (row,
+// point) forms the split fluxes, one lane per (row, field, split) does one
+// reconstruction, one lane per (row, field) adds R+ + R- to finish D.
+constexpr int kXBoundRows = 32;
+
 template <class R, int S>
-__global__ void __launch_bounds__(256) k_xbound(StageArgs<R> a) {
+__global__ void __launch_bounds__(kXBoundRows * 10) k_xbound(StageArgs<R> a) {
+  __shared__ R sF[kXBoundRows][8][10];
+  __shared__ R sR[kXBoundRows][10];
   const int nx = a.g.n[0];
   const long long rows = (long long)a.g.n[1] * a.g.n[2];
-  const long long row = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (row >= rows) return;
   const long long nc = a.g.nc;
-  const long long rowbase = row * nx;
+  const int t = threadIdx.x;
   unsigned fix = 0;
-  R fp[5][8], fm[5][8];
+  if (t < kXBoundRows * 8) {
+    const int l = t >> 3, m = t & 7;
+    const long long row = (long long)blockIdx.x * kXBoundRows + l;
+    if (row < rows) {
+      R u[5];
+      load5(a.W, nc, row * nx + map_idx(nx - 4 + m, nx, 0), u);
+      const PrimV pv = c2p(u, fix);
+      R Fp[5], Fm[5];
+      split_flux<R, 0>(u, pv, Fp, Fm);
 #pragma unroll
-  for (int m = 0; m < 8; ++m) {
-    const int src = map_idx(nx - 4 + m, nx, 0);
-    R u[5];
-    load5(a.W, nc, rowbase + src, u);
-    const PrimV pv = c2p(u, fix);
-    R Fp[5], Fm[5];
-    split_flux<R, 0>(u, pv, Fp, Fm);
-#pragma unroll
-    for (int c = 0; c < 5; ++c) {
-      fp[c][m] = Fp[c];
-      fm[c][m] = Fm[c];
+      for (int c = 0; c < 5; ++c) {
+        sF[l][m][c] = Fp[c];
+        sF[l][m][5 + c] = Fm[c];
+      }
     }
   }
-#pragma unroll
-  for (int c = 0; c < 5; ++c) {
-    const R r = face_flux<R, S>(fp[c], fm[c], a.eps);
-    R* d = a.D + c * nc + rowbase + nx - 1;
-    *d = (*d - r) * a.inv_d;
+  __syncthreads();
+  {
+    const int l = t / 10, r = t % 10, c = r >> 1;
+    const long long row = (long long)blockIdx.x * kXBoundRows + l;
+    if (row < rows) {
+      sR[l][r] = (r & 1) == 0
+                     ? weno7<R, S>(sF[l][0][c], sF[l][1][c], sF[l][2][c], sF[l][3][c], sF[l][4][c], sF[l][5][c],
+                                   sF[l][6][c], a.eps)
+                     : weno7<R, S>(sF[l][7][5 + c], sF[l][6][5 + c], sF[l][5][5 + c], sF[l][4][5 + c],
+                                   sF[l][3][5 + c], sF[l][2][5 + c], sF[l][1][5 + c], a.eps);
+    }
+  }
+  __syncthreads();
+  if (t < kXBoundRows * 5) {
+    const int l = t / 5, c = t % 5;
+    const long long row = (long long)blockIdx.x * kXBoundRows + l;
+    if (row < rows) {
+      const R r = sR[l][2 * c] + sR[l][2 * c + 1];
+      R* d = a.D + c * nc + row * nx + nx - 1;
+      *d = (*d - r) * a.inv_d;
+    }
   }
   add_fixups(a.fixups, fix);
 }
@@ -799,8 +821,8 @@ void launch_xbound_t(const StageArgs<R>& base, hipStream_t st) {
   StageArgs<R> a = base;
   a.inv_d = R(1.0 / a.g.dx[0]);
   const long long rows = (long long)a.g.n[1] * a.g.n[2];
-  const unsigned nb = (unsigned)((rows + 255) / 256);
-  hipLaunchKernelGGL((k_xbound<R, S>), dim3(nb), dim3(256), 0, st, a);
+  const unsigned nb = (unsigned)((rows + kXBoundRows - 1) / kXBoundRows);
+  hipLaunchKernelGGL((k_xbound<R, S>), dim3(nb), dim3(kXBoundRows * 10), 0, st, a);
 }
 
 template <class R, int S, int AX>
