@@ -39,11 +39,23 @@ METRIC = "cell-updates/s per RK3 stage at 256^3 (% of roofline); adjoint/forward
 #   flux and Lax-Friedrichs split per cell and axis 25;
 #   divergence 10 per axis; conserved->primitive 25 (counted once, x);
 #   RK combine 15 (z).
-FLOPS_PER_CELL = {
-    "xface": 1550 + 25 + 10 + 25,
-    "ymarch": 1550 + 25 + 10,
-    "zmarch": 1550 + 25 + 10 + 15,
-}
+# Flops per reconstruction for the other schemes, same accounting: WENO7-JS
+# drops tau (151); WENO5-Z: candidates 15, smoothness 45, tau 2, weights 15,
+# sum 2, combination 5, normalisation 1 = 85; WENO5-JS 83; linear weights:
+# candidates + combination (35 for WENO7, 20 for WENO5).
+RECON_FLOPS = {"z": 155, "js": 151, "linear": 35, "z5": 85, "js5": 83, "linear5": 20}
+
+
+SCHEME_NAMES = {"z": "WENO7-Z", "js": "WENO7-JS", "linear": "WENO7 linear weights", "z5": "WENO5-Z",
+                "js5": "WENO5-JS", "linear5": "WENO5 linear weights"}
+
+
+def flops_per_cell(weno: str = "z"):
+    r = 10 * RECON_FLOPS[weno]
+    return {"xface": r + 25 + 10 + 25, "ymarch": r + 25 + 10, "zmarch": r + 25 + 10 + 15}
+
+
+FLOPS_PER_CELL = flops_per_cell("z")
 FLOPS_PER_CELL_UPDATE = sum(FLOPS_PER_CELL.values())  # 4795
 # Algorithmic words moved per cell by each kernel (W read + D read/write;
 # z: + U^n read in stages 2-3 (2/3 on average) + output write).
@@ -212,6 +224,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--yz", choices=["tile", "march"], default="tile", help="y/z face kernels")
     ap.add_argument("--x", choices=["row", "tile"], default="row", help="x face kernel")
+    ap.add_argument("--weno", choices=sorted(RECON_FLOPS), default="z",
+                    help="reconstruction: WENO7 (z, js, linear) or WENO5 (z5, js5, linear5)")
     ap.add_argument("--adjoint-n", type=int, default=128, help="grid edge of the differentiable run (0: skip)")
     ap.add_argument("--adjoint-steps", type=int, default=100)
     ap.add_argument("--adjoint-ckpt", type=int, default=10)
@@ -245,7 +259,9 @@ def main():
         return
 
     w = W.paper_event(2, n=(args.n,) * 3)
-    h = H.from_workload(w, precision=args.precision)
+    h = H.from_workload(w, precision=args.precision, weno=args.weno)
+    fpc = flops_per_cell(args.weno)
+    fpc_update = sum(fpc.values())
     h.set_option(H.OPT_YZ_KERNEL, 0 if args.yz == "tile" else 1)
     h.set_option(H.OPT_X_KERNEL, 0 if args.x == "row" else 1)
     nc = w.n[0] * w.n[1] * w.n[2]
@@ -272,12 +288,12 @@ def main():
 
     value = nc * 3 * args.steps / (ms * 1e-3)
     per_kernel = {k: {"ms_per_launch": (t / n if n else 0.0), "launches": n} for k, (t, n) in prof.items()}
-    dom = max(FLOPS_PER_CELL, key=lambda k: prof[k][0])
+    dom = max(fpc, key=lambda k: prof[k][0])
     t_launch = prof[dom][0] / prof[dom][1]
-    achieved = FLOPS_PER_CELL[dom] * nc / (t_launch * 1e-3) / 1e12
+    achieved = fpc[dom] * nc / (t_launch * 1e-3) / 1e12
     peak = PEAK_TFLOPS[args.precision]
     traffic = None
-    rec = MEASURED_TRAFFIC.get((dom, args.precision, args.yz, args.n))
+    rec = MEASURED_TRAFFIC.get((dom, args.precision, args.yz, args.n)) if args.weno == "z" else None
     if rec is not None:
         import hashlib
         src = os.path.join(ROOT, "paper_1511_02137_amd", "csrc", "hydro_kernels.hip")
@@ -286,8 +302,8 @@ def main():
     roofline = {"bound": "alu", "kernel": dom, "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
                 "frac": achieved / peak, "traffic": traffic,
                 "algorithmic_bytes": BYTES_PER_CELL[dom] * (8 if args.precision == "f64" else 4) * nc,
-                "flops_per_cell": FLOPS_PER_CELL[dom]}
-    step_frac = FLOPS_PER_CELL_UPDATE * value / 1e12 / peak
+                "flops_per_cell": fpc[dom]}
+    step_frac = fpc_update * value / 1e12 / peak
 
     out = {
         "metric": METRIC,
@@ -304,13 +320,13 @@ def main():
         "vs_baseline": None,
         "dtype": args.precision,
         "data": "synthetic",
-        "config": {"workload": "%s: %d^3 cells, dx 0.1 fm, dt 0.02 fm/c, p = e/3, WENO7-Z + LF split, "
-                               "SSP-RK3, 1 jet (NGP), outflow" % (w.name, args.n),
+        "config": {"workload": "%s: %d^3 cells, dx 0.1 fm, dt 0.02 fm/c, p = e/3, %s + LF split, "
+                               "SSP-RK3, 1 jet (NGP), outflow" % (w.name, args.n, SCHEME_NAMES[args.weno]),
                    "grid": list(w.n), "precision": args.precision, "jets": len(w.jets), "yz_kernel": args.yz,
-                   "x_kernel": args.x},
+                   "x_kernel": args.x, "weno": args.weno},
         "roofline": roofline,
         "step_alu_frac": step_frac,
-        "flops_per_cell_update": FLOPS_PER_CELL_UPDATE,
+        "flops_per_cell_update": fpc_update,
         "kernels": per_kernel,
         "fixups": fix,
     }

@@ -65,7 +65,19 @@ typedef enum {
 } hydro_deposit;
 
 /* Nonlinear weights of the 7th-order WENO reconstruction. */
-typedef enum { HYDRO_WENO_Z = 0, HYDRO_WENO_JS = 1, HYDRO_WENO_LINEAR = 2 } hydro_weno;
+/* Reconstruction: 7th-order WENO (the paper's scheme) with WENO-Z, Jiang-Shu
+ * or linear weights; or the 5th-order WENO the paper names as its
+ * alternative (section "Simulation setup"), same weight variants, stencil
+ * a_{i-2}..a_{i+2}, ideal weights (1, 6, 3)/10, WENO-Z tau = |b0 - b2|.
+ * hydro_adjoint_step supports the WENO7 schemes only. */
+typedef enum {
+  HYDRO_WENO_Z = 0,
+  HYDRO_WENO_JS = 1,
+  HYDRO_WENO_LINEAR = 2,
+  HYDRO_WENO5_Z = 3,
+  HYDRO_WENO5_JS = 4,
+  HYDRO_WENO5_LINEAR = 5
+} hydro_weno;
 
 typedef struct {
   int32_t n[3];        /* cells along x, y, z >= 1; n[0] <= 810 (FP64) or 1024 (FP32),

@@ -223,6 +223,10 @@ int step_impl(hydro_ctx* ctx, R* U, int nsteps, hipStream_t st) {
 }
 
 bool adjoint_fits(const hydro_config* c, std::string* why) {
+  if (c->weno > 2) {
+    if (why) *why = "the adjoint is built for the WENO7 schemes only";
+    return false;
+  }
   for (int d = 0; d < 3; ++d) {
     const size_t lds = (size_t)line_adj_lds_elems(c->n[d]) * elem_size(c);
     if (lds > 65536 || c->n[d] > 1024) {

@@ -133,8 +133,62 @@ __device__ __forceinline__ double div_nr(double num, double den) {
   return fma(fma(-den, q, num), r, q);
 }
 
+// WENO5 value at x_{i+1/2} from the left, b0..b4 = a_{i-2}..a_{i+2}, in the
+// same form as weno7: candidates d_k (q_k - a_i) from first differences
+// (d = (1, 6, 3)/10), Jiang-Shu indicators b_k = c1^2 + 13/12 D2^2 + eps with
+// c1 = D1 + h_k D2 (h = 3/2, 1/2, -1/2), WENO-Z tau = |b0 - b2|.
+template <class R, int S>
+__device__ __forceinline__ R weno5(R b0, R b1, R b2, R b3, R b4, R eps) {
+  const R e0 = b1 - b0, e1 = b2 - b1, e2 = b3 - b2, e3 = b4 - b3;
+  const R r0 = fma(R(5.0 / 60.0), e1, R(-2.0 / 60.0) * e0);
+  const R r1 = fma(R(2.0 / 10.0), e2, R(1.0 / 10.0) * e1);
+  const R r2 = fma(R(-1.0 / 20.0), e3, R(4.0 / 20.0) * e2);
+  if (S == kWeno5Linear) return b2 + ((r0 + r1) + r2);
+  const R f0 = e1 - e0, f1 = e2 - e1, f2 = e3 - e2;
+  const R s0 = fma(R(1.5), f0, e0), s1 = fma(R(0.5), f1, e1), s2 = fma(R(-0.5), f2, e2);
+  const R be0 = fma(s0, s0, fma(R(13.0 / 12.0) * f0, f0, eps));
+  const R be1 = fma(s1, s1, fma(R(13.0 / 12.0) * f1, f1, eps));
+  const R be2 = fma(s2, s2, fma(R(13.0 / 12.0) * f2, f2, eps));
+  if (sizeof(R) == 8) {
+    // common denominator: with B_k = b_k^2, WENO-Z d_k (B_k + tau^2) prod_{j!=k} B_j,
+    // Jiang-Shu d_k prod_{j!=k} B_j
+    const R B0 = be0 * be0, B1 = be1 * be1, B2 = be2 * be2;
+    R A0 = B1 * B2, A1 = B0 * B2, A2 = B0 * B1;
+    if (S == kWeno5Z) {
+      const R tau = fabs(be0 - be2);
+      const R t2 = tau * tau;
+      A0 = (B0 + t2) * A0;
+      A1 = (B1 + t2) * A1;
+      A2 = (B2 + t2) * A2;
+    }
+    const R num = fma(A2, r2, fma(A1, r1, A0 * r0));
+    const R den = fma(A2, R(0.3), fma(A1, R(0.6), A0 * R(0.1)));
+    return b2 + (R)div_nr((double)num, (double)den);
+  } else {
+    const R i0 = rcp_approx<R>(be0), i1 = rcp_approx<R>(be1), i2 = rcp_approx<R>(be2);
+    R w0, w1, w2;
+    if (S == kWeno5Z) {
+      const R tau = fabs(be0 - be2);
+      const R s0z = tau * i0, s1z = tau * i1, s2z = tau * i2;
+      w0 = fma(s0z, s0z, R(1));
+      w1 = fma(s1z, s1z, R(1));
+      w2 = fma(s2z, s2z, R(1));
+    } else {
+      w0 = i0 * i0;
+      w1 = i1 * i1;
+      w2 = i2 * i2;
+    }
+    const R num = fma(w2, r2, fma(w1, r1, w0 * r0));
+    const R den = fma(w2, R(0.3), fma(w1, R(0.6), w0 * R(0.1)));
+    return fma(num, rcp_approx<R>(den), b2);
+  }
+}
+
+// Schemes kWeno5*: the 5th-order reconstruction from the middle five values
+// (a_{i-2}..a_{i+2}) of the same 7-point window.
 template <class R, int S>
 __device__ __forceinline__ R weno7(R a0, R a1, R a2, R a3, R a4, R a5, R a6, R eps) {
+  if (S >= kWeno5Z) return weno5<R, S>(a1, a2, a3, a4, a5, eps);
   // nested differences of the seven values
   const R e0 = a1 - a0, e1 = a2 - a1, e2 = a3 - a2, e3 = a4 - a3, e4 = a5 - a4, e5 = a6 - a5;
   // candidates as d_k (q_k - a3), from the differences

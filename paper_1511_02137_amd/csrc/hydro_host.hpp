@@ -37,7 +37,7 @@ inline bool config_ok(const hydro_config* c, std::string* why) {
   if (c->n[1] > 65535 || c->n[2] > 65535) return fail("n[1], n[2] must be <= 65535");
   if (!(c->dt > 0.0) || !std::isfinite(c->dt) || !std::isfinite(c->t0)) return fail("dt must be > 0");
   if (c->precision != HYDRO_F64 && c->precision != HYDRO_F32) return fail("bad precision");
-  if (c->weno < 0 || c->weno > 2) return fail("bad weno");
+  if (c->weno < 0 || c->weno > 5) return fail("bad weno");
   if (c->deposit != HYDRO_DEP_NGP && c->deposit != HYDRO_DEP_GAUSS) return fail("bad deposit");
   if (!(c->weno_eps > 0.0)) return fail("weno_eps must be > 0");
   if (c->weno_p != 2) return fail("only weno_p = 2 is built");

@@ -13,7 +13,8 @@ constexpr double kEFloor = 1e-12;  // E at or below: vacuum fix-up
 constexpr double kVCap = 1.0 - 1e-10;  // |v| cap of the fix-up
 constexpr int kSumBlocks = 1024;   // fixed number of reduction blocks (fixed order)
 
-enum Scheme { kWenoZ = 0, kWenoJS = 1, kWenoLinear = 2 };
+// WENO7 with Z, Jiang-Shu or linear weights; 3..5: the same for WENO5.
+enum Scheme { kWenoZ = 0, kWenoJS = 1, kWenoLinear = 2, kWeno5Z = 3, kWeno5JS = 4, kWeno5Linear = 5 };
 
 // Grid of one event.
 struct Grid {

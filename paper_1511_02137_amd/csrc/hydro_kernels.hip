@@ -876,12 +876,13 @@ hipError_t launch_face_kernel(int kernel, const StageArgs<R>& a, int scheme, int
     case 5: launch_tile_t<R, S, 2>(a, st); break;          \
     default: launch_xtile_t<R, S>(a, st); break;           \
   }
-  if (scheme == kWenoJS) {
-    HYDRO_DISPATCH(kWenoJS)
-  } else if (scheme == kWenoLinear) {
-    HYDRO_DISPATCH(kWenoLinear)
-  } else {
-    HYDRO_DISPATCH(kWenoZ)
+  switch (scheme) {
+    case kWenoJS: HYDRO_DISPATCH(kWenoJS) break;
+    case kWenoLinear: HYDRO_DISPATCH(kWenoLinear) break;
+    case kWeno5Z: HYDRO_DISPATCH(kWeno5Z) break;
+    case kWeno5JS: HYDRO_DISPATCH(kWeno5JS) break;
+    case kWeno5Linear: HYDRO_DISPATCH(kWeno5Linear) break;
+    default: HYDRO_DISPATCH(kWenoZ) break;
   }
 #undef HYDRO_DISPATCH
   return hipGetLastError();
@@ -935,12 +936,13 @@ hipError_t launch_batch_axis(int AX, const BatchArgs<R>& b, int scheme, long lon
   if (AX == 0) hipLaunchKernelGGL((k_btile<R, S, 0>), grid, tb, lds, st, b);            \
   else if (AX == 1) hipLaunchKernelGGL((k_btile<R, S, 1>), grid, tb, lds, st, b);       \
   else hipLaunchKernelGGL((k_btile<R, S, 2>), grid, tb, lds, st, b);
-  if (scheme == kWenoJS) {
-    HYDRO_BAXIS(kWenoJS)
-  } else if (scheme == kWenoLinear) {
-    HYDRO_BAXIS(kWenoLinear)
-  } else {
-    HYDRO_BAXIS(kWenoZ)
+  switch (scheme) {
+    case kWenoJS: HYDRO_BAXIS(kWenoJS) break;
+    case kWenoLinear: HYDRO_BAXIS(kWenoLinear) break;
+    case kWeno5Z: HYDRO_BAXIS(kWeno5Z) break;
+    case kWeno5JS: HYDRO_BAXIS(kWeno5JS) break;
+    case kWeno5Linear: HYDRO_BAXIS(kWeno5Linear) break;
+    default: HYDRO_BAXIS(kWenoZ) break;
   }
 #undef HYDRO_BAXIS
   return hipGetLastError();

@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(_PKG, "libhydro.so")
 HYDRO_OK, HYDRO_EINVAL, HYDRO_ENOMEM, HYDRO_EDEVICE, HYDRO_ENONPHYS, HYDRO_ESTATE = 0, -1, -2, -3, -4, -5
 F64, F32 = 0, 1
 BC = {"outflow": 0, "periodic": 1}
-WENO = {"z": 0, "js": 1, "linear": 2}
+WENO = {"z": 0, "js": 1, "linear": 2, "z5": 3, "js5": 4, "linear5": 5}
 DEPOSIT = {"ngp": 0, "gauss": 1}
 
 EXPORTED = [

@@ -1,0 +1,113 @@
+"""GPU parity of the 5th-order WENO variant (the alternative the paper names
+beside WENO7): the library's HYDRO_WENO5_* schemes against the oracle's
+weno5 on the same seeded inputs, with the same bars as the WENO7 parity
+tests (FP64 relative L-infinity 1e-12 per field; FP32 relative L2 of e and
+|v|), plus launch-shape and batch bitwise identity and the adjoint's refusal.
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_1511_02137_amd import workloads as W
+from test_gpu_parity import fp32_errors, oracle_jets, rel_linf, report, run_gpu, run_oracle
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def need_gpu():
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a GPU")
+    from paper_1511_02137_amd import hydro as H
+    H.load_library()
+
+
+def H():
+    from paper_1511_02137_amd import hydro
+    return hydro
+
+
+def test_small_event_weno5_fp64_matches_oracle():
+    w = W.small_event(1)
+    pb, st = run_oracle(w, 10, weno="z5")
+    h = run_gpu(w, 10, weno="z5")
+    err = rel_linf(h.U.cpu().numpy(), st.U)
+    report("WENO5-Z small event 32^3 x 10", err)
+    assert np.all(err <= 1e-12), err
+    assert h.sums()[5] == pytest.approx(st.ledger, rel=1e-12)
+
+
+@pytest.mark.parametrize("weno", ["js5", "linear5"])
+@pytest.mark.parametrize("n,bc", [((37, 29, 23), "outflow"), ((33, 17, 40), "periodic")])
+def test_weno5_variants_and_ragged_grids_fp64(weno, n, bc):
+    w = W.small_event(4, n=n, steps=4)
+    w.jets[0].x0 = (-0.5, 0.0123, -0.0071)
+    pb, st = run_oracle(w, 4, bc=(bc,) * 3, weno=weno)
+    h = run_gpu(w, 4, bc=(bc,) * 3, weno=weno)
+    err = rel_linf(h.U.cpu().numpy(), st.U)
+    report("%s %s %s" % (weno, n, bc), err)
+    assert np.all(err <= 1e-12), err
+
+
+@pytest.mark.parametrize("bc,tol", [("periodic", 1e-5), ("outflow", 1e-4)])
+def test_small_event_weno5_fp32_matches_oracle(bc, tol):
+    w = W.small_event(1)
+    pb, st = run_oracle(w, 10, bc=(bc,) * 3, weno="z5")
+    h = run_gpu(w, 10, precision="f32", bc=(bc,) * 3, weno="z5")
+    e_err, v_err = fp32_errors(h.U.cpu().numpy(), st.U, pb)
+    print("WENO5 FP32 small event %s: rel L2 e %.2e |v| %.2e" % (bc, e_err, v_err), flush=True)
+    assert e_err <= tol and v_err <= tol
+
+
+def test_weno5_rhs_fp64_matches_oracle():
+    w = W.small_event(6, n=(30, 26, 22))
+    w.deposit = "gauss"
+    w.jets[0].x0 = (-0.8345, 0.031, 0.013)
+    pb = O.Problem(n=w.n, weno="z5", deposit="gauss")
+    jets = oracle_jets(w)
+    U = O.run(pb, O.prim_to_cons(pb, w.prim0), 2, jets).U
+    t = 1.0 + 2 * 0.02 + 0.01
+    Lo, _, _ = O.rhs(pb, U, t, jets)
+    h = H().from_workload(w, weno="z5")
+    Lg = h.rhs(torch.from_numpy(U).cuda(), t).cpu().numpy()
+    err = np.abs(Lg - Lo).max() / np.abs(Lo).max()
+    print("WENO5 rhs: max |dL|/max|L| %.2e" % err, flush=True)
+    assert err <= 1e-14
+
+
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+def test_weno5_launch_shapes_and_batch_bitwise(precision):
+    w = W.small_event(7, n=(45, 38, 40), steps=3)
+    outs = []
+    for yz, xk in ((0, 0), (1, 0), (0, 1)):
+        h = H().from_workload(w, precision=precision, weno="z5")
+        h.set_option(H().OPT_YZ_KERNEL, yz)
+        h.set_option(H().OPT_X_KERNEL, xk)
+        h.step(3)
+        torch.cuda.synchronize()
+        outs.append(h.U.clone())
+        h.close()
+    for u in outs[1:]:
+        assert torch.equal(outs[0], u)
+    b = H().batch_from_workloads([w, W.small_event(8, n=(20, 33, 12))], precision=precision, weno="z5")
+    b.run(3)
+    torch.cuda.synchronize()
+    assert torch.equal(b.U[0], outs[0])
+    b.close()
+
+
+def test_adjoint_refuses_weno5():
+    w = W.small_gradient_event(n=(16, 16, 16), steps=2)
+    cfg = H().make_config(w.n, weno="z5")
+    assert H().workspace_bytes(cfg, 0) > 0
+    assert H().workspace_bytes(cfg, 2) == 0  # no adjoint workspace for WENO5
+    with pytest.raises(H().HydroError):
+        H().from_workload(w, weno="z5", adjoint_k=2)
+    h = H().from_workload(w, weno="z5")
+    lam = torch.zeros_like(h.U)
+    grad = torch.zeros((1, 5), dtype=torch.float64, device="cuda")
+    with pytest.raises(H().HydroError):
+        h.adjoint_step(h.U.clone(), 0, [w.jets[0].E0], 1, lam, grad)
+    h.close()
