@@ -44,18 +44,29 @@ __global__ void __launch_bounds__(TB) k_xface(StageArgs<R> a) {
   const long long rowbase = (long long)blockIdx.x * nx;
   unsigned fix = 0;
 
-  for (int t = threadIdx.x; t < nx + 8; t += TB) {
-    const int j = (t < nx) ? t + 4 : (t < nx + 4 ? t - nx : t);
-    const int src = map_idx(j - 4, nx, a.g.bc[0]);
+  // each lane recovers its own cell once and also stores it into every ghost
+  // slot that copies it (outflow: the edge cells, periodic: the wrapped ones)
+  if (threadIdx.x < nx) {
+    const int x = threadIdx.x;
     R u[5];
-    load5(a.W, nc, rowbase + src, u);
+    load5(a.W, nc, rowbase + x, u);
     const PrimV pv = c2p(u, fix);
     R Fp[5], Fm[5];
     split_flux<R, 0>(u, pv, Fp, Fm);
 #pragma unroll
     for (int c = 0; c < 5; ++c) {
-      sFp[c * P + j] = Fp[c];
-      sFm[c * P + j] = Fm[c];
+      sFp[c * P + x + 4] = Fp[c];
+      sFm[c * P + x + 4] = Fm[c];
+    }
+    for (int g = 0; g < 8; ++g) {
+      const int j = g < 4 ? g : nx + g;  // ghost slots 0..3 and nx+4..nx+7
+      if (map_idx(j - 4, nx, a.g.bc[0]) == x) {
+#pragma unroll
+        for (int c = 0; c < 5; ++c) {
+          sFp[c * P + j] = Fp[c];
+          sFm[c * P + j] = Fm[c];
+        }
+      }
     }
   }
   __syncthreads();
