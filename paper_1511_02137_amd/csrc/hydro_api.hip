@@ -290,10 +290,13 @@ int adjoint_impl(hydro_ctx* ctx, const R* Uc, int64_t step0, const double* E0, i
       a.lW = (k == 3) ? lamA : (k == 2 ? lamB : lam);
       a.W = st_ptr(i, k - 1);
       a.mu = lY;
-      // x starts G, y adds, the jet source adds at its cells, z adds and
-      // applies the reverse RK combine (lW, acc)
-      for (int ax = 0; ax < 3; ++ax) {
-        if (ax == 2 && ctx->njet > 0) {
+      // y starts G, z adds, the jet source adds at its cells, x adds and
+      // applies the reverse RK combine (x lines are contiguous in memory, so
+      // the combine's five extra fields are read and written coalesced)
+      const int order[3] = {1, 2, 0};
+      for (int step_ax = 0; step_ax < 3; ++step_ax) {
+        const int ax = order[step_ax];
+        if (step_ax == 2 && ctx->njet > 0) {
           JetAdjArgs j;
           j.W = a.W;
           j.mu = lY;
@@ -310,8 +313,8 @@ int adjoint_impl(hydro_ctx* ctx, const R* Uc, int64_t step0, const double* E0, i
           j.hbarc = c.hbarc;
           HYDRO_TRY(launch_jet_adj<R>(j, st));
         }
-        a.first = ax == 0 ? 1 : 0;
-        a.stage = ax == 2 ? k : 0;
+        a.first = step_ax == 0 ? 1 : 0;
+        a.stage = step_ax == 2 ? k : 0;
         ProfScope p(ctx, HYDRO_K_ADJ, st);
         HYDRO_TRY(launch_adj_axis<R>(ax, a, c.weno, st));
       }
