@@ -208,6 +208,7 @@ def batch_throughput(precision: str, steps: int, warmup: int, cache):
                        "one graph replay per step" % (len(ws), precision, steps),
            "cells": cells, "ms_per_step": ms / steps, "value": cells * 3 * steps / (ms * 1e-3),
            "unit": "cell-updates/s", "blocks_per_axis": [b.get_option(a) for a in (0, 1, 2)],
+           "x_form": "rows" if b.get_option(H.BOPT_X_ROWS) else "tiles",
            "tuned_from_cache": from_cache, "fixups": b.fixups()}
     b.close()
     return out

@@ -253,8 +253,9 @@ void hydro_destroy(hydro_ctx* ctx);
  * boundaries, deposit and jets) advanced together, as an ensemble of the
  * paper's problem.  The events must share precision, weno, weno_eps and
  * weno_p.  Per RK stage there is one launch per axis whose workgroups walk
- * the tiles of every event (x: 32 x 16 cells, y and z: 16 x 32), one launch
- * for the jets of every event, and per step one FP64 reduction launch; each
+ * the work items of every event (x: 31/32 x 16-cell tiles or groups of whole
+ * rows, y and z: 16 x 31/32-cell tiles), one launch for the jets of every
+ * event, and per step one FP64 reduction launch; each
  * face is computed with the same arithmetic as hydro_rk3_step, so every
  * event evolves exactly as it would alone.  Stage times come from a device
  * step counter; the launches of one step are captured once into a HIP graph
@@ -295,19 +296,22 @@ typedef enum {
   HYDRO_BOPT_BLOCKS_X = 0,  /* workgroups of the x launch: 0 = one per tile, else a persistent grid */
   HYDRO_BOPT_BLOCKS_Y = 1,
   HYDRO_BOPT_BLOCKS_Z = 2,
-  HYDRO_BOPT_GRAPH = 3      /* 1 (default): replay a captured graph per step; 0: direct launches */
+  HYDRO_BOPT_GRAPH = 3,     /* 1 (default): replay a captured graph per step; 0: direct launches */
+  HYDRO_BOPT_X_ROWS = 4     /* x faces: 0 (default) = 31/32 x 16 LDS tiles; 1 = groups of whole rows
+                               plus a launch for the outflow x faces */
 } hydro_batch_option;
 
 int hydro_batch_set_option(hydro_batch* b, int option, long long value);
 int hydro_batch_get_option(hydro_batch* b, int option, long long* value);
 
-/* Pick the workgroup count of each axis launch: the candidates 0 (one per
- * tile) and c * (number of CUs), c in {1, 2, 3, 4, 6, 8}, are timed on this
- * batch (median of 5 launches of the right-hand-side form, no state change)
- * and the fastest kept.  cache_path (may be NULL) is a text file of
- * "key bx by bz" lines, the key a hash of the GPU, precision, scheme and the
- * sorted event shapes: a hit skips the timing (*from_cache = 1), a miss
- * appends the picks.  Synchronous. */
+/* Pick the x-face form (tiles or whole rows) and the workgroup count of each
+ * axis launch: the candidates 0 (one per work item) and c * (number of CUs),
+ * c in {1, 2, 3, 4, 6, 8}, are timed on this batch (median of 5 launches of
+ * the right-hand-side form, no state change) and the fastest kept.
+ * cache_path (may be NULL) is a text file of "key bx by bz xrows" lines, the
+ * key a hash of the GPU, precision, scheme and the sorted event shapes: a hit
+ * skips the timing (*from_cache = 1), a miss appends the picks.
+ * Synchronous. */
 int hydro_batch_autotune(hydro_batch* b, const char* cache_path, void* stream, int* from_cache);
 
 /* Synchronous: sums of event `event` as hydro_sums (ledger in out[5]). */

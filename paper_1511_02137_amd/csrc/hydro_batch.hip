@@ -1,9 +1,10 @@
 // hydro_batch.hip -- host side of the batch API of include/hydro.h: many
 // independent events (uneven grids, their own jets) advanced together.
 //
-// Per stage there is one launch per axis whose workgroups walk the tiles of
-// every event (a persistent grid of a few workgroups per CU, or one workgroup
-// per tile), one launch for the jets of every event, and per step one FP64
+// Per stage there is one launch per axis whose workgroups walk the work items
+// of every event (x: groups of whole rows, y/z: LDS tiles; a persistent grid
+// of a few workgroups per CU, or one workgroup per item), one launch for the
+// outflow x faces and one for the jets of every event, and per step one FP64
 // reduction launch and a device step counter (stage times are computed on the
 // device from it).  The launches of one step are captured once into a HIP
 // graph and the graph is replayed for every step.  The grid size of each axis
@@ -34,14 +35,17 @@ struct hydro_batch {
   std::vector<std::vector<hydro_jet>> jets;
   std::vector<BatchEvent> ev;      // host copy of the device table
   BatchEvent* d_ev = nullptr;      // device table [n]
-  long long* d_off = nullptr;      // device item offsets [3][n + 1]
+  long long* d_off = nullptr;      // device item offsets [5][n + 1] (x tiles, y, z, x rows, x boundary)
   std::vector<long long> off;      // host copy
   DevScalars* d_dev = nullptr;     // per-event device scalars [n]
   double* d_part = nullptr;        // reduction partials [n][kSumBlocks][5]
   long long* d_step = nullptr;     // device step counter
   int64_t step = 0;
   int cus = 256;
-  long long blocks[3] = {0, 0, 0}; // workgroups per axis launch (0: one per tile)
+  long long blocks[3] = {0, 0, 0}; // workgroups per axis launch (0: one per item)
+  int xrows = 0;                   // x pass: 0 LDS tiles, 1 groups of whole rows (+ boundary faces)
+  int xtb = 256;                   // x-row workgroup size
+  long long xlds = 0;              // its dynamic LDS
   int use_graph = 1;
   hipStream_t cap = nullptr;       // capture stream (never runs work)
   hipGraphExec_t exec = nullptr;
@@ -86,14 +90,23 @@ BatchArgs<R> batch_args(const hydro_batch* b, int AX, int stage) {
   a.n_events = b->n;
   a.stage = stage;
   a.eps = (R)b->cfg[0].weno_eps;
+  a.xtb = b->xtb;
+  a.xlds = b->xlds;
   return a;
 }
 
-// One stage of every event: x tiles, y tiles, jets, z tiles (+ RK combine).
+// One stage of every event: x tiles (or x rows and the outflow x faces),
+// y tiles, jets, z tiles (+ RK combine).
 template <class R>
 hipError_t stage_launches(hydro_batch* b, int stage, hipStream_t st) {
   const int scheme = b->cfg[0].weno;
-  hipError_t e = launch_batch_axis<R>(0, batch_args<R>(b, 0, stage), scheme, b->blocks[0], st);
+  hipError_t e;
+  if (b->xrows) {
+    e = launch_batch_axis<R>(3, batch_args<R>(b, 3, stage), scheme, b->blocks[0], st);
+    if (e == hipSuccess) e = launch_batch_axis<R>(4, batch_args<R>(b, 4, stage), scheme, 0, st);
+  } else {
+    e = launch_batch_axis<R>(0, batch_args<R>(b, 0, stage), scheme, b->blocks[0], st);
+  }
   if (e == hipSuccess) e = launch_batch_axis<R>(1, batch_args<R>(b, 1, stage), scheme, b->blocks[1], st);
   if (e == hipSuccess) e = launch_batch_jet<R>(batch_args<R>(b, 0, stage), st);
   if (e == hipSuccess) e = launch_batch_axis<R>(2, batch_args<R>(b, 2, stage), scheme, b->blocks[2], st);
@@ -160,7 +173,8 @@ std::string tune_key(const hydro_batch* b) {
   return out;
 }
 
-bool cache_lookup(const char* path, const std::string& key, long long blocks[3]) {
+// Cache lines: "key bx by bz xrows".
+bool cache_lookup(const char* path, const std::string& key, long long blocks[3], int* xrows) {
   if (!path) return false;
   std::ifstream f(path);
   std::string line;
@@ -168,19 +182,20 @@ bool cache_lookup(const char* path, const std::string& key, long long blocks[3])
   while (std::getline(f, line)) {  // the last entry for a key wins
     std::istringstream ls(line);
     std::string k;
-    long long v[3];
-    if (ls >> k >> v[0] >> v[1] >> v[2] && k == key) {
+    long long v[4];
+    if (ls >> k >> v[0] >> v[1] >> v[2] >> v[3] && k == key) {
       for (int a = 0; a < 3; ++a) blocks[a] = v[a];
+      *xrows = v[3] ? 1 : 0;
       found = true;
     }
   }
   return found;
 }
 
-void cache_store(const char* path, const std::string& key, const long long blocks[3]) {
+void cache_store(const char* path, const std::string& key, const long long blocks[3], int xrows) {
   if (!path) return;
   std::ofstream f(path, std::ios::app);
-  f << key << " " << blocks[0] << " " << blocks[1] << " " << blocks[2] << "\n";
+  f << key << " " << blocks[0] << " " << blocks[1] << " " << blocks[2] << " " << xrows << "\n";
 }
 
 // Median time (ms) of `reps` launches of one axis kernel in right-hand-side
@@ -220,14 +235,27 @@ template <class R>
 int autotune_impl(hydro_batch* b, const char* cache, hipStream_t st, int* from_cache) {
   const std::string key = tune_key(b);
   long long best[3];
-  if (cache_lookup(cache, key, best)) {
+  int xr = 0;
+  if (cache_lookup(cache, key, best, &xr)) {
     for (int a = 0; a < 3; ++a) b->blocks[a] = best[a];
+    b->xrows = xr;
     if (from_cache) *from_cache = 1;
     drop_graph(b);
     return HYDRO_OK;
   }
   const long long cand[] = {0, 1, 2, 3, 4, 6, 8};
-  for (int AX = 0; AX < 3; ++AX) {
+  // x: LDS tiles (item list 0) or groups of whole rows (3) plus the outflow
+  // faces (4, one workgroup per item, timed once); y and z: tiles (1, 2)
+  const int lists[4] = {0, 3, 1, 2};
+  float xbound = 0.f;
+  {
+    hipError_t e = time_axis<R>(b, 4, 0, 5, st, &xbound);
+    if (e != hipSuccess) return bhip(b, e, "autotune launch");
+  }
+  float tx[2] = {1e30f, 1e30f};
+  long long bx[2] = {0, 0};
+  for (int li = 0; li < 4; ++li) {
+    const int AX = lists[li];
     float tbest = 1e30f;
     long long pick = 0;
     for (long long c : cand) {
@@ -235,14 +263,22 @@ int autotune_impl(hydro_batch* b, const char* cache, hipStream_t st, int* from_c
       float ms = 0.f;
       hipError_t e = time_axis<R>(b, AX, blocks, 5, st, &ms);
       if (e != hipSuccess) return bhip(b, e, "autotune launch");
+      if (AX == 3) ms += xbound;
       if (ms < tbest) {
         tbest = ms;
         pick = blocks;
       }
     }
-    b->blocks[AX] = pick;
+    if (AX == 0 || AX == 3) {
+      tx[AX == 3] = tbest;
+      bx[AX == 3] = pick;
+    } else {
+      b->blocks[AX] = pick;
+    }
   }
-  cache_store(cache, key, b->blocks);
+  b->xrows = tx[1] < tx[0] ? 1 : 0;
+  b->blocks[0] = bx[b->xrows];
+  cache_store(cache, key, b->blocks, b->xrows);
   if (from_cache) *from_cache = 0;
   drop_graph(b);
   return HYDRO_OK;
@@ -299,7 +335,7 @@ int hydro_batch_create(const hydro_config* cfgs, int n_events, const double* con
     return code;
   };
   hipError_t e = hipMalloc(&b->d_ev, sizeof(BatchEvent) * n_events);
-  if (e == hipSuccess) e = hipMalloc(&b->d_off, sizeof(long long) * 3 * (n_events + 1));
+  if (e == hipSuccess) e = hipMalloc(&b->d_off, sizeof(long long) * 5 * (n_events + 1));
   if (e == hipSuccess) e = hipMalloc(&b->d_dev, sizeof(DevScalars) * n_events);
   if (e == hipSuccess) e = hipMalloc(&b->d_part, sizeof(double) * (size_t)n_events * kSumBlocks * 5);
   if (e == hipSuccess) e = hipMalloc(&b->d_step, sizeof(long long));
@@ -309,7 +345,16 @@ int hydro_batch_create(const hydro_config* cfgs, int n_events, const double* con
 
   unsigned char* ws = static_cast<unsigned char*>(workspace);
   b->ev.resize(n_events);
-  b->off.assign((size_t)3 * (n_events + 1), 0);
+  b->off.assign((size_t)5 * (n_events + 1), 0);
+  {
+    std::vector<int> nxs(n_events);
+    for (int i = 0; i < n_events; ++i) nxs[i] = cfgs[i].n[0];
+    const int elem = (int)elem_size(&cfgs[0]);
+    b->xtb = xrow_block(nxs.data(), n_events, elem);
+    b->xlds = 0;
+    for (int i = 0; i < n_events; ++i)
+      b->xlds = std::max<long long>(b->xlds, (long long)xrow_lds_bytes(nxs[i], xrow_rows(nxs[i], b->xtb, elem), elem));
+  }
   for (int i = 0; i < n_events; ++i) {
     const hydro_config& c = cfgs[i];
     BatchEvent& v = b->ev[i];
@@ -331,8 +376,9 @@ int hydro_batch_create(const hydro_config* cfgs, int n_events, const double* con
     v.hbarc = c.hbarc;
     v.njet = 0;
     v.deposit = c.deposit;
-    for (int a = 0; a < 3; ++a)
-      b->off[(size_t)a * (n_events + 1) + i + 1] = b->off[(size_t)a * (n_events + 1) + i] + batch_items(a, v.g);
+    for (int a = 0; a < 5; ++a)
+      b->off[(size_t)a * (n_events + 1) + i + 1] =
+          b->off[(size_t)a * (n_events + 1) + i] + batch_items(a, v.g, b->xtb, (int)elem_size(&c));
   }
   std::vector<DevScalars> zero(n_events);
   std::memset(zero.data(), 0, sizeof(DevScalars) * n_events);
@@ -461,6 +507,11 @@ int hydro_batch_set_option(hydro_batch* b, int option, long long value) {
       if (value != 0 && value != 1) return bfail(b, HYDRO_EINVAL, "HYDRO_BOPT_GRAPH takes 0 or 1");
       b->use_graph = (int)value;
       return HYDRO_OK;
+    case HYDRO_BOPT_X_ROWS:
+      if (value != 0 && value != 1) return bfail(b, HYDRO_EINVAL, "HYDRO_BOPT_X_ROWS takes 0 or 1");
+      b->xrows = (int)value;
+      drop_graph(b);
+      return HYDRO_OK;
     default:
       return bfail(b, HYDRO_EINVAL, "unknown batch option");
   }
@@ -473,6 +524,7 @@ int hydro_batch_get_option(hydro_batch* b, int option, long long* value) {
     case HYDRO_BOPT_BLOCKS_Y:
     case HYDRO_BOPT_BLOCKS_Z: *value = b->blocks[option - HYDRO_BOPT_BLOCKS_X]; return HYDRO_OK;
     case HYDRO_BOPT_GRAPH: *value = b->use_graph; return HYDRO_OK;
+    case HYDRO_BOPT_X_ROWS: *value = b->xrows; return HYDRO_OK;
     default: return bfail(b, HYDRO_EINVAL, "unknown batch option");
   }
 }

@@ -99,6 +99,6 @@ template <class R>
 hipError_t launch_batch_jet(const BatchArgs<R>& b, hipStream_t st);
 template <class R>
 hipError_t launch_batch_sums(const BatchArgs<R>& b, long long* step, hipStream_t st);
-long long batch_items(int AX, const Grid& g);
+long long batch_items(int AX, const Grid& g, int xtb, int elem);
 
 }  // namespace hydro

@@ -79,6 +79,43 @@ __host__ __device__ constexpr int tile_len(int n) {
   return ((n + 30) / 31) * 31 * 100 < 112 * (((n + 31) / 32) * 32) ? 31 : 32;
 }
 
+// x-row kernels: workgroup of TB lanes holding TB / nx whole rows.  LDS per
+// row: max(10 (nx + 8), 5 nx) words.  xrow_block picks TB in {256, 384, 512,
+// 1024} for a set of row lengths: every nx <= TB, the LDS of TB / nx rows
+// <= 64 KiB, and the fewest lane slots for the cells (ties: the smaller TB).
+__host__ __device__ inline size_t xrow_lds_bytes(int nx, int rpi, int elem) {
+  const int per_row = 10 * (nx + 8) > 5 * nx ? 10 * (nx + 8) : 5 * nx;
+  return (size_t)rpi * per_row * elem;
+}
+
+// Rows per workgroup of TB lanes: TB / nx, fewer if their LDS exceeds 64 KiB.
+__host__ __device__ inline int xrow_rows(int nx, int TB, int elem) {
+  int rpi = TB / nx;
+  while (rpi > 1 && xrow_lds_bytes(nx, rpi, elem) > 65536) --rpi;
+  return rpi;
+}
+
+inline int xrow_block(const int* nxs, int count, int elem) {
+  const int cand[4] = {256, 384, 512, 1024};
+  int best = 1024;
+  double best_cost = 1e300;
+  for (int k = 0; k < 4; ++k) {
+    const int TB = cand[k];
+    bool ok = true;
+    double cost = 0.0;
+    for (int e = 0; e < count && ok; ++e) {
+      const int nx = nxs[e];
+      if (nx > TB) ok = false;
+      else cost += (double)TB / (double)(xrow_rows(nx, TB, elem) * nx);  // lane slots per cell
+    }
+    if (ok && cost < best_cost * (1.0 - 1e-12)) {
+      best_cost = cost;
+      best = TB;
+    }
+  }
+  return best;
+}
+
 // One event of a batch (device table, see hydro_batch.hip).
 struct BatchEvent {
   Grid g;
@@ -107,6 +144,8 @@ struct BatchArgs {
   int n_events;
   int stage;              // 1..3; 0: L written to U1 (no state change)
   R eps;
+  int xtb;                // workgroup size of the x-row launch (rows per item: xtb / nx)
+  long long xlds;         // its dynamic LDS bytes (the largest event)
 };
 
 // Arguments of the line adjoint kernels (device pointers).

@@ -8,8 +8,9 @@
 //   combine: Shu-Osher SSP-RK3.
 //
 // Work split (all kernels of a stage run on one stream):
-//   k_xface   one workgroup per x-row.  Each lane recovers primitives for its
-//             cell, stores the split x-fluxes of the row plus 4+4 ghost cells
+//   k_xface   one workgroup per group of whole x-rows.  Each lane recovers
+//             primitives for its cell, stores the split x-fluxes of the row
+//             plus 4+4 ghost cells
 //             in LDS, reconstructs its left face and writes the x-divergence.
 //   k_xbound  the right boundary face of every row (outflow x only).
 //   k_march   lanes along x (coalesced), each lane marches along y or z over
@@ -30,24 +31,29 @@
 namespace hydro {
 
 // ---------------------------------------------------------------------------
-// x-faces: one workgroup per row (blockDim = nx rounded up to 64).
-// LDS slot j holds the split fluxes of padded position p = j - 4.
-template <class R, int S, int TB>
-__global__ void __launch_bounds__(TB) k_xface(StageArgs<R> a) {
-  extern __shared__ __align__(16) unsigned char smem_raw[];
-  R* s = reinterpret_cast<R*>(smem_raw);
+// x-faces: a workgroup owns rpi = blockDim / nx whole rows (row0, row0 + 1,
+// ...; fewer at the end of the grid).  LDS per row: the split fluxes of its nx
+// cells and 8 ghost slots (slot j holds padded position j - 4), then the face
+// values.  One lane per cell: it recovers its cell, stores the split fluxes
+// (also into every ghost slot that copies the cell), reconstructs the cell's
+// left face and forms the divergence; the outflow right face of the last cell
+// is added by k_xbound.
+template <class R, int S>
+__device__ __forceinline__ void xrows_body(const StageArgs<R>& a, long long row0, int rpi, R* s) {
   const int nx = a.g.n[0];
   const int P = nx + 8;
-  R* sFp = s;
-  R* sFm = s + 5 * P;
+  const long long rows = (long long)a.g.n[1] * a.g.n[2];
   const long long nc = a.g.nc;
-  const long long rowbase = (long long)blockIdx.x * nx;
+  const int r = threadIdx.x / nx;
+  const int x = threadIdx.x - r * nx;
+  const long long row = row0 + r;
+  const bool act = r < rpi && row < rows;
+  const long long rowbase = row * nx;
+  R* sFp = s + (size_t)r * 10 * P;
+  R* sFm = sFp + 5 * P;
   unsigned fix = 0;
 
-  // each lane recovers its own cell once and also stores it into every ghost
-  // slot that copies it (outflow: the edge cells, periodic: the wrapped ones)
-  if (threadIdx.x < nx) {
-    const int x = threadIdx.x;
+  if (act) {
     R u[5];
     load5(a.W, nc, rowbase + x, u);
     const PrimV pv = c2p(u, fix);
@@ -71,21 +77,20 @@ __global__ void __launch_bounds__(TB) k_xface(StageArgs<R> a) {
   }
   __syncthreads();
 
-  const int x = threadIdx.x;
   R Fh[5];
-  if (x < nx) {
+  if (act) {
     // face x - 1/2: F+ at x-4..x+2 (slots x..x+6), F- at x-3..x+3 (slots x+1..x+7)
 #pragma unroll
     for (int c = 0; c < 5; ++c) Fh[c] = face_flux<R, S>(sFp + c * P + x, sFm + c * P + x, a.eps);
   }
   __syncthreads();
-  R* sF = s;  // [5][nx]
-  if (x < nx) {
+  R* sF = s + (size_t)r * 5 * nx;  // [5][nx] per row
+  if (act) {
 #pragma unroll
     for (int c = 0; c < 5; ++c) sF[c * nx + x] = Fh[c];
   }
   __syncthreads();
-  if (x < nx) {
+  if (act) {
     const bool last = (x + 1 == nx);
 #pragma unroll
     for (int c = 0; c < 5; ++c) {
@@ -103,6 +108,12 @@ __global__ void __launch_bounds__(TB) k_xface(StageArgs<R> a) {
   add_fixups(a.fixups, fix);
 }
 
+template <class R, int S, int TB>
+__global__ void __launch_bounds__(TB) k_xface(StageArgs<R> a, int rpi) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  xrows_body<R, S>(a, (long long)blockIdx.x * rpi, rpi, reinterpret_cast<R*>(smem_raw));
+}
+
 // Right boundary face of every row (outflow x): points nx-4..nx+3 (the last
 // four copies of cell nx-1).  A workgroup takes 32 rows: one lane per (row,
 // point) forms the split fluxes, one lane per (row, field, split) does one
@@ -110,7 +121,7 @@ __global__ void __launch_bounds__(TB) k_xface(StageArgs<R> a) {
 constexpr int kXBoundRows = 32;
 
 template <class R, int S>
-__global__ void __launch_bounds__(kXBoundRows * 10) k_xbound(StageArgs<R> a) {
+__device__ __forceinline__ void xbound_body(const StageArgs<R>& a, long long group) {
   __shared__ R sF[kXBoundRows][8][10];
   __shared__ R sR[kXBoundRows][10];
   const int nx = a.g.n[0];
@@ -120,7 +131,7 @@ __global__ void __launch_bounds__(kXBoundRows * 10) k_xbound(StageArgs<R> a) {
   unsigned fix = 0;
   if (t < kXBoundRows * 8) {
     const int l = t >> 3, m = t & 7;
-    const long long row = (long long)blockIdx.x * kXBoundRows + l;
+    const long long row = group * kXBoundRows + l;
     if (row < rows) {
       R u[5];
       load5(a.W, nc, row * nx + map_idx(nx - 4 + m, nx, 0), u);
@@ -137,7 +148,7 @@ __global__ void __launch_bounds__(kXBoundRows * 10) k_xbound(StageArgs<R> a) {
   __syncthreads();
   {
     const int l = t / 10, r = t % 10, c = r >> 1;
-    const long long row = (long long)blockIdx.x * kXBoundRows + l;
+    const long long row = group * kXBoundRows + l;
     if (row < rows) {
       sR[l][r] = (r & 1) == 0
                      ? weno7<R, S>(sF[l][0][c], sF[l][1][c], sF[l][2][c], sF[l][3][c], sF[l][4][c], sF[l][5][c],
@@ -149,7 +160,7 @@ __global__ void __launch_bounds__(kXBoundRows * 10) k_xbound(StageArgs<R> a) {
   __syncthreads();
   if (t < kXBoundRows * 5) {
     const int l = t / 5, c = t % 5;
-    const long long row = (long long)blockIdx.x * kXBoundRows + l;
+    const long long row = group * kXBoundRows + l;
     if (row < rows) {
       const R r = sR[l][2 * c] + sR[l][2 * c + 1];
       R* d = a.D + c * nc + row * nx + nx - 1;
@@ -157,6 +168,11 @@ __global__ void __launch_bounds__(kXBoundRows * 10) k_xbound(StageArgs<R> a) {
     }
   }
   add_fixups(a.fixups, fix);
+}
+
+template <class R, int S>
+__global__ void __launch_bounds__(kXBoundRows * 10) k_xbound(StageArgs<R> a) {
+  xbound_body<R, S>(a, blockIdx.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -748,6 +764,7 @@ __device__ __forceinline__ double batch_stage_time(const BatchEvent& ev, long lo
   return tn + c * ev.dt;
 }
 
+// x, y or z tiles of every event (xtile_body, tile_body).
 template <class R, int S, int AX>
 __global__ void __launch_bounds__(512) k_btile(BatchArgs<R> b) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -770,6 +787,34 @@ __global__ void __launch_bounds__(512) k_btile(BatchArgs<R> b) {
       else tile_body<R, S, AX, AX == 2, 32>(a, bx, by, bz, s);
     }
     __syncthreads();  // the next item overwrites the LDS tile
+  }
+}
+
+// x rows of every event: items are groups of TB / nx rows (xrows_body).
+template <class R, int S, int TB>
+__global__ void __launch_bounds__(TB) k_bxrows(BatchArgs<R> b) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  R* s = reinterpret_cast<R*>(smem_raw);
+  for (long long it = blockIdx.x; it < b.items; it += gridDim.x) {
+    const int e = batch_event_of(b.off, b.n_events, it);
+    const BatchEvent& ev = b.ev[e];
+    const int rpi = xrow_rows(ev.g.n[0], TB, (int)sizeof(R));
+    const StageArgs<R> a = batch_stage_args<R>(ev, b.stage, b.eps, 0);
+    xrows_body<R, S>(a, (it - b.off[e]) * rpi, rpi, s);
+    __syncthreads();  // the next item overwrites the LDS rows
+  }
+}
+
+// Outflow right x-face of every event with outflow x: items are groups of
+// kXBoundRows rows (xbound_body).
+template <class R, int S>
+__global__ void __launch_bounds__(kXBoundRows * 10) k_bxbound(BatchArgs<R> b) {
+  for (long long it = blockIdx.x; it < b.items; it += gridDim.x) {
+    const int e = batch_event_of(b.off, b.n_events, it);
+    const BatchEvent& ev = b.ev[e];
+    const StageArgs<R> a = batch_stage_args<R>(ev, b.stage, b.eps, 0);
+    xbound_body<R, S>(a, it - b.off[e]);
+    __syncthreads();
   }
 }
 
@@ -818,12 +863,17 @@ void launch_xface_t(const StageArgs<R>& base, hipStream_t st) {
   StageArgs<R> a = base;
   const int nx = a.g.n[0];
   a.inv_d = R(1.0 / a.g.dx[0]);
-  const size_t lds = (size_t)max(10 * (nx + 8), 5 * nx) * sizeof(R);
-  const unsigned rows = (unsigned)((long long)a.g.n[1] * a.g.n[2]);
-  if (nx <= 256) {
-    hipLaunchKernelGGL((k_xface<R, S, 256>), dim3(rows), dim3(256), lds, st, a);
-  } else {
-    hipLaunchKernelGGL((k_xface<R, S, 1024>), dim3(rows), dim3(1024), lds, st, a);
+  const int n1 = nx;
+  const int TB = xrow_block(&n1, 1, (int)sizeof(R));
+  const int rpi = xrow_rows(nx, TB, (int)sizeof(R));
+  const size_t lds = xrow_lds_bytes(nx, rpi, (int)sizeof(R));
+  const long long rows = (long long)a.g.n[1] * a.g.n[2];
+  const unsigned nb = (unsigned)((rows + rpi - 1) / rpi);
+  switch (TB) {
+    case 256: hipLaunchKernelGGL((k_xface<R, S, 256>), dim3(nb), dim3(256), lds, st, a, rpi); break;
+    case 384: hipLaunchKernelGGL((k_xface<R, S, 384>), dim3(nb), dim3(384), lds, st, a, rpi); break;
+    case 512: hipLaunchKernelGGL((k_xface<R, S, 512>), dim3(nb), dim3(512), lds, st, a, rpi); break;
+    default: hipLaunchKernelGGL((k_xface<R, S, 1024>), dim3(nb), dim3(1024), lds, st, a, rpi); break;
   }
 }
 
@@ -927,26 +977,48 @@ hipError_t launch_primitives(const R* U, R* prim, long long nc, double g, double
   return hipGetLastError();
 }
 
-// Items per axis of one event (tiles of the batched kernels).
-long long batch_items(int AX, const Grid& g) {
+// Work items of one event for the batched launches: 0 x tiles, 1 and 2 y/z
+// tiles, 3 x-row groups of xrow_rows(nx, xtb) rows, 4 groups of kXBoundRows
+// rows for the outflow x face (none for periodic x).  An x pass is either 0
+// or 3 + 4.
+long long batch_items(int AX, const Grid& g, int xtb, int elem) {
+  const long long rows = (long long)g.n[1] * g.n[2];
+  if (AX == 3) {
+    const int rpi = xrow_rows(g.n[0], xtb, elem);
+    return (rows + rpi - 1) / rpi;
+  }
+  if (AX == 4) return g.bc[0] ? 0 : (rows + kXBoundRows - 1) / kXBoundRows;
   const int A = tile_len(g.n[AX]);
   if (AX == 0) return (long long)((g.n[0] + A - 1) / A) * ((g.n[1] + kXTileY - 1) / kXTileY) * g.n[2];
   const int no = AX == 1 ? g.n[2] : g.n[1];
   return (long long)((g.n[0] + kTileX - 1) / kTileX) * ((g.n[AX] + A - 1) / A) * no;
 }
 
-// blocks: workgroups of the axis kernel (0: one per item).
+// blocks: workgroups of the launch (0: one per item).
 template <class R>
 hipError_t launch_batch_axis(int AX, const BatchArgs<R>& b, int scheme, long long blocks, hipStream_t st) {
   const long long nb = (blocks <= 0 || blocks > b.items) ? b.items : blocks;
   if (nb <= 0) return hipSuccess;
-  const size_t lds = (size_t)2 * 5 * (32 + 8) * 16 * sizeof(R);  // the largest tile (A = 32)
-  static_assert(kXTileY == 16 && kTileXP == 16, "tile LDS sizes");
+  const size_t lds = (size_t)2 * 5 * (32 + 8) * 16 * sizeof(R);  // the largest y/z tile (A = 32)
   const dim3 grid((unsigned)nb), tb(512);
-#define HYDRO_BAXIS(S)                                                                  \
-  if (AX == 0) hipLaunchKernelGGL((k_btile<R, S, 0>), grid, tb, lds, st, b);            \
-  else if (AX == 1) hipLaunchKernelGGL((k_btile<R, S, 1>), grid, tb, lds, st, b);       \
-  else hipLaunchKernelGGL((k_btile<R, S, 2>), grid, tb, lds, st, b);
+  const size_t xl = (size_t)b.xlds;
+#define HYDRO_BAXIS(S)                                                                                      \
+  if (AX == 3) {                                                                                            \
+    switch (b.xtb) {                                                                                        \
+      case 256: hipLaunchKernelGGL((k_bxrows<R, S, 256>), grid, dim3(256), xl, st, b); break;                 \
+      case 384: hipLaunchKernelGGL((k_bxrows<R, S, 384>), grid, dim3(384), xl, st, b); break;                 \
+      case 512: hipLaunchKernelGGL((k_bxrows<R, S, 512>), grid, dim3(512), xl, st, b); break;                 \
+      default: hipLaunchKernelGGL((k_bxrows<R, S, 1024>), grid, dim3(1024), xl, st, b); break;                \
+    }                                                                                                       \
+  } else if (AX == 4) {                                                                                     \
+    hipLaunchKernelGGL((k_bxbound<R, S>), grid, dim3(kXBoundRows * 10), 0, st, b);                          \
+  } else if (AX == 0) {                                                                                     \
+    hipLaunchKernelGGL((k_btile<R, S, 0>), grid, tb, lds, st, b);                                          \
+  } else if (AX == 1) {                                                                                     \
+    hipLaunchKernelGGL((k_btile<R, S, 1>), grid, tb, lds, st, b);                                          \
+  } else {                                                                                                  \
+    hipLaunchKernelGGL((k_btile<R, S, 2>), grid, tb, lds, st, b);                                          \
+  }
   switch (scheme) {
     case kWenoJS: HYDRO_BAXIS(kWenoJS) break;
     case kWenoLinear: HYDRO_BAXIS(kWenoLinear) break;

@@ -32,7 +32,7 @@ EXPORTED = [
     "hydro_batch_destroy",
 ]
 OPT_YZ_KERNEL, OPT_MARCH_SEG, OPT_X_KERNEL = 0, 1, 2
-BOPT_BLOCKS_X, BOPT_BLOCKS_Y, BOPT_BLOCKS_Z, BOPT_GRAPH = 0, 1, 2, 3
+BOPT_BLOCKS_X, BOPT_BLOCKS_Y, BOPT_BLOCKS_Z, BOPT_GRAPH, BOPT_X_ROWS = 0, 1, 2, 3, 4
 KERNELS = ["xface", "xbound", "ymarch", "jet", "zmarch", "sums", "adjoint"]
 
 

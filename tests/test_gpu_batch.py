@@ -98,11 +98,11 @@ def test_launch_shapes_and_graph_do_not_change_results():
     ref.set_option(H().BOPT_GRAPH, 0)
     for a in (H().BOPT_BLOCKS_X, H().BOPT_BLOCKS_Y, H().BOPT_BLOCKS_Z):
         ref.set_option(a, 0)  # one workgroup per tile
-    shapes = [(1, 1, 1), (7, 3, 5), (256, 512, 1024)]
+    shapes = [(1, 1, 1, 0), (7, 3, 5, 0), (256, 512, 1024, 0), (0, 0, 0, 1), (5, 2, 3, 1)]
     others = []
     for sh in shapes:
         b = H().batch_from_workloads(ws, precision="f64")
-        for a, v in zip((H().BOPT_BLOCKS_X, H().BOPT_BLOCKS_Y, H().BOPT_BLOCKS_Z), sh):
+        for a, v in zip((H().BOPT_BLOCKS_X, H().BOPT_BLOCKS_Y, H().BOPT_BLOCKS_Z, H().BOPT_X_ROWS), sh):
             b.set_option(a, v)
         others.append(b)
     # graph replays interleaved with eager work and synchronisation, each compared
@@ -125,10 +125,11 @@ def test_autotune_cache_and_bitwise_results(tmp_path):
     b = H().batch_from_workloads(ws, precision="f32")
     assert b.autotune(cache) is False
     picks = [b.get_option(a) for a in (0, 1, 2)]
-    assert os.path.exists(cache) and len(open(cache).read().split()) == 4
+    assert os.path.exists(cache) and len(open(cache).read().split()) == 5
     b2 = H().batch_from_workloads(ws, precision="f32")
     assert b2.autotune(cache) is True
     assert [b2.get_option(a) for a in (0, 1, 2)] == picks
+    assert b2.get_option(H().BOPT_X_ROWS) == b.get_option(H().BOPT_X_ROWS)
     b.run(3)
     torch.cuda.synchronize()
     assert_batch_equals_single(b, ws, 3, "f32")
