@@ -21,6 +21,7 @@ Parity status per function (pins in tests/test_oracle_*.py):
   sums             pinned (numpy sum)
   eps2             pinned (closed form on a separable field)
   eps2_complex_step pinned (central finite differences of run)
+  jvp              pinned (central finite differences of run)
 """
 from __future__ import annotations
 
@@ -99,8 +100,9 @@ def _load():
     lib.oracle_eps2.argtypes = [cp, dp, dp]
     lib.oracle_eps2_complex_step.argtypes = [cp, jp, ctypes.c_int, dp, ctypes.c_int, ctypes.c_int,
                                              ctypes.c_int, ctypes.c_double, dp, dp, dp]
+    lib.oracle_jvp.argtypes = [cp, jp, ctypes.c_int, dp, dp, ctypes.c_int, ctypes.c_double, dp, dp]
     for name in ("oracle_prim_to_cons", "oracle_cons_to_prim", "oracle_rhs", "oracle_run",
-                 "oracle_sums", "oracle_eps2", "oracle_eps2_complex_step"):
+                 "oracle_sums", "oracle_eps2", "oracle_eps2_complex_step", "oracle_jvp"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -300,3 +302,17 @@ def eps2_complex_step(pb: Problem, prim0: np.ndarray, nsteps: int, jets, which: 
                                           ctypes.byref(val), ctypes.byref(der))
     assert rc == 0
     return val.value, der.value
+
+
+def jvp(pb: Problem, U0: np.ndarray, V: np.ndarray, nsteps: int, jets=None, h: float = 1e-30):
+    """(U(nsteps), J V) of nsteps steps from step 0 by the complex-step method:
+    the run from U0 + i h V, jets at their E0."""
+    U0 = np.ascontiguousarray(U0, dtype=np.float64).reshape(5, *pb.shape)
+    V = np.ascontiguousarray(V, dtype=np.float64).reshape(5, *pb.shape)
+    arr, nj = _jets(jets)
+    Uo = np.empty_like(U0)
+    JV = np.empty_like(U0)
+    c = pb.c()
+    rc = _load().oracle_jvp(ctypes.byref(c), arr, nj, _dp(U0), _dp(V), int(nsteps), float(h), _dp(Uo), _dp(JV))
+    assert rc == 0
+    return Uo, JV

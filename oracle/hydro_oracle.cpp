@@ -781,4 +781,28 @@ int oracle_eps2_complex_step(const ocfg* c, const ojet* jets, int njet, const do
   return 0;
 }
 
+// Directional derivative of nsteps steps from step 0 by the complex-step
+// method: the run from U0 + i h V (jets at their E0) gives U(nsteps) as the
+// real part and J V = Im / h, with J the Jacobian of the state after nsteps
+// with respect to the initial conserved state.  Arrays [5][ncell].
+int oracle_jvp(const ocfg* c, const ojet* jets, int njet, const double* U0, const double* V,
+               int nsteps, double h, double* Uout, double* JV) {
+  if (!valid(c) || njet < 0 || nsteps < 0 || !(h > 0.0)) return -1;
+  size_t m = 5 * (size_t)c->n[0] * c->n[1] * c->n[2];
+  std::vector<cplx> U(m);
+  for (size_t q = 0; q < m; ++q) U[q] = cplx(U0[q], h * V[q]);
+  std::vector<Jet<cplx>> cj;
+  for (int j = 0; j < njet; ++j) cj.push_back(to_jet<cplx>(jets[j]));
+  std::vector<cplx> Ej(njet);
+  for (int j = 0; j < njet; ++j) Ej[j] = cplx(jets[j].E0, 0.0);
+  cplx ledger(0.0, 0.0);
+  long long fx = 0;
+  run_impl<cplx>(c, nullptr, njet, U.data(), nsteps, 0, Ej.data(), &ledger, &fx, &cj);
+  for (size_t q = 0; q < m; ++q) {
+    Uout[q] = U[q].real();
+    JV[q] = U[q].imag() / h;
+  }
+  return 0;
+}
+
 }  // extern "C"

@@ -86,3 +86,27 @@ def test_complex_step_matches_finite_differences_initial_field(setup, kind, h, t
     pm[0] -= h * de
     fd = (eps2_run(pb, pp, jets, STEPS) - eps2_run(pb, pm, jets, STEPS)) / (2 * h)
     assert abs(der - fd) <= tol * abs(der), (der, fd)
+
+
+@pytest.mark.parametrize("bc", ["outflow", "periodic"])
+def test_jvp_matches_finite_differences(bc):
+    """The oracle's complex-step Jacobian-vector product of whole steps against
+    central differences of its real runs, in a smooth direction of all five
+    fields."""
+    w = W.small_gradient_event(n=(12, 10, 8), steps=3)
+    w.jets[0].x0 = (-0.2345, 0.031, 0.013)
+    pb = O.Problem(n=w.n, bc=(bc,) * 3, deposit="gauss")
+    jets = [O.Jet(**j.__dict__) for j in w.jets]
+    U0 = O.prim_to_cons(pb, w.prim0)
+    V = np.stack([smooth_direction(pb.shape, 20 + f) for f in range(5)]) * np.abs(U0).max(axis=(1, 2, 3))[:, None, None, None]
+    Ur, JV = O.jvp(pb, U0, V, 3, jets)
+    Ureal = O.run(pb, U0, 3, jets).U  # complex division and roots round differently
+    assert np.abs(Ur - Ureal).max() <= 1e-13 * np.abs(Ureal).max()
+    # WENO-Z weights on the flat outflow ghosts bend sharply (beta ~ h^2 against
+    # eps = 1e-6), so the differences converge only for h <= 1e-7 there.
+    h = 1e-8
+    Up = O.run(pb, U0 + h * V, 3, jets).U
+    Um = O.run(pb, U0 - h * V, 3, jets).U
+    fd = (Up - Um) / (2 * h)
+    err = np.abs(fd - JV).max() / np.abs(JV).max()
+    assert err <= 1e-6, err
