@@ -271,3 +271,43 @@ def test_differentiable_run_matches_full_size_complex_step_fixture():
         rel = abs(g32["jets"][0, k] - ref) / abs(ref)
         print("FP32 %s: rel %.2e" % (which, rel))
         assert rel <= bar, (which, rel)
+
+
+# --- the whole Jacobian: dot products against the oracle's forward mode ---------------------------------------------
+
+@pytest.mark.parametrize("weno", ["z", "js", "linear"])
+@pytest.mark.parametrize("bc", ["outflow", "periodic"])
+def test_adjoint_step_dot_product_with_oracle_jvp(weno, bc):
+    """<J^T W, V> from hydro_adjoint_step against <W, J V> from the oracle's
+    complex-step forward mode, J the Jacobian of three whole steps (all five
+    fields, jet deposit and depletion included) at the same U0, W and V
+    smooth in every field.  Both sides are exact derivatives of the discrete
+    map, so they agree to rounding: bar 1e-10 of the sum of |products|."""
+    from paper_1511_02137_amd import hydro as H
+    steps = 3
+    w = small(n=(21, 18, 16), steps=steps)
+    pb = O.Problem(n=w.n, dx=w.dx, t0=w.t0, dt=w.dt, bc=(bc,) * 3, deposit=w.deposit, weno=weno)
+    U0 = O.prim_to_cons(pb, w.prim0)
+    amp = np.abs(U0).max(axis=(1, 2, 3))[:, None, None, None]
+    V = np.stack([smooth_direction(pb.shape, 40 + f) for f in range(5)]) * amp
+    Wt = np.stack([smooth_direction(pb.shape, 60 + f) for f in range(5)]) / amp
+    _, JV = O.jvp(pb, U0, V, steps, oracle_jets(w))
+    print("dot product", weno, bc, w.n, flush=True)
+    h = H.from_workload(w, precision="f64", weno=weno, bc=(bc,) * 3, adjoint_k=steps)
+    lam = torch.tensor(Wt, dtype=torch.float64, device="cuda")
+    grad = torch.zeros((1, 5), dtype=torch.float64, device="cuda")
+    Uc = torch.tensor(U0, dtype=torch.float64, device="cuda")
+    h.adjoint_step(Uc, 0, [w.jets[0].E0], steps, lam, grad)
+    torch.cuda.synchronize()
+    lam0 = lam.cpu().numpy()
+    h.close()
+    lhs = np.sum(lam0 * V)
+    rhs = np.sum(Wt * JV)
+    scale = np.sum(np.abs(Wt * JV))
+    assert abs(lhs - rhs) <= 1e-10 * scale, (lhs, rhs, scale)
+    # per field: the adjoint of each field's block row, same bar
+    for f in range(5):
+        Vf = np.zeros_like(V)
+        Vf[f] = V[f]
+        _, JVf = O.jvp(pb, U0, Vf, steps, oracle_jets(w))
+        assert abs(np.sum(lam0[f] * V[f]) - np.sum(Wt * JVf)) <= 1e-10 * scale, f
