@@ -209,12 +209,18 @@ int hydro_adjoint_step(hydro_ctx* ctx, const void* U_ckpt, int64_t step0, const 
  * (dU/dprim)^T lambda, i.e. d/de, d/dvx, d/dvy, d/dvz, d/dn. */
 int hydro_init_vjp(hydro_ctx* ctx, const double* prim0, const void* lambda, double* grad_prim, void* stream);
 
-/* Launch-shape options of a context (results do not depend on them: every
- * variant computes each face with the same arithmetic). */
+/* Options of a context.  The launch shapes (0-2) do not change results: every
+ * variant computes each face with the same arithmetic.  HYDRO_OPT_ADJ_SKIP_N
+ * = 1 makes hydro_adjoint_step take the N component of lambda as zero on
+ * entry, skip N's reverse reconstructions and return a zero N component: N
+ * enters no other field's flux and no source, so for a loss that does not
+ * depend on N (eps2 depends on e and v only) the result is the same as with
+ * 0 (the default) and the line adjoints do 4/5 of the reconstruction work. */
 typedef enum {
   HYDRO_OPT_YZ_KERNEL = 0,  /* y/z faces: 0 = LDS tiles (default), 1 = register marches */
   HYDRO_OPT_MARCH_SEG = 1,  /* cells per march segment (default 32) */
-  HYDRO_OPT_X_KERNEL = 2    /* x faces: 0 = one row per workgroup (default), 1 = 32 x 16 LDS tiles */
+  HYDRO_OPT_X_KERNEL = 2,   /* x faces: 0 = one row per workgroup (default), 1 = 32 x 16 LDS tiles */
+  HYDRO_OPT_ADJ_SKIP_N = 3  /* 0 (default) or 1, see above */
 } hydro_option;
 
 /* Set / read an option; HYDRO_EINVAL for an unknown option or bad value. */

@@ -42,6 +42,8 @@ class Eps2Problem:
         self.steps = int(workload.steps)
         self.k = int(ckpt_every)
         self.h = H.from_workload(workload, precision=precision, adjoint_k=self.k, device=device)
+        # eps2 depends on e and v only, so the adjoint of N is zero throughout
+        self.h.set_option(H.OPT_ADJ_SKIP_N, 1)
         self.prim = torch.tensor(workload.prim0, dtype=torch.float64, device=device)
         self.jet = workload.jets[0]
 

@@ -377,7 +377,7 @@ __global__ void __launch_bounds__(TBMAX) k_line_adj(AdjArgs<R> a) {
   if (tid < n) {
 #pragma unroll
     for (int c = 0; c < 5; ++c) {
-      my[c] = a.mu[c * nc + base + (long long)tid * stride];
+      my[c] = (c == 4 && a.skip_n) ? R(0) : a.mu[c * nc + base + (long long)tid * stride];
       sX[c * n + tid] = my[c];
     }
   }
@@ -400,6 +400,11 @@ __global__ void __launch_bounds__(TBMAX) k_line_adj(AdjArgs<R> a) {
   R acc[2][2][5];  // [point][split][field]
 #pragma unroll
   for (int c = 0; c < 5; ++c) {
+    if (c == 4 && a.skip_n) {  // uniform over the workgroup
+#pragma unroll
+      for (int q = 0; q < 2; ++q) acc[q][0][c] = acc[q][1][c] = R(0);
+      continue;
+    }
     if (tid < n) {
       R args[7], ab[7];
 #pragma unroll
@@ -533,7 +538,7 @@ __global__ void __launch_bounds__(kBoundLines * 10) k_bound_adj(AdjArgs<R> a) {
     if (L < nlines) {
       long long stride;
       const long long base = line_base(AX, L, a.g, stride);
-      const R phi = -a.mu[c * nc + base + (long long)(n - 1) * stride] * a.inv_d;
+      const R phi = (c == 4 && a.skip_n) ? R(0) : -a.mu[c * nc + base + (long long)(n - 1) * stride] * a.inv_d;
       R args[7], ab[7];
       if (sp == 0) {
 #pragma unroll

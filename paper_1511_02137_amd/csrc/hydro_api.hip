@@ -49,6 +49,7 @@ struct hydro_ctx {
   int seg = 32;      // march segment length
   int yz_tile = 1;   // 1: y/z faces from LDS tiles, 0: register-window marches
   int x_tile = 0;    // 1: x faces from 32 x 16 LDS tiles, 0: one row per workgroup
+  int adj_skip_n = 0;  // 1: the adjoint sweep takes lambda_N as zero and skips N
   std::string err;
   // per-kernel timing (hydro_profile): event pairs recorded around launches
   bool prof = false;
@@ -281,6 +282,7 @@ int adjoint_impl(hydro_ctx* ctx, const R* Uc, int64_t step0, const double* E0, i
   a.dt = (R)dt;
   a.acc = acc;
   a.stage = 0;
+  a.skip_n = ctx->adj_skip_n;
   const double cst[3] = {0.0, 1.0, 0.5};
   const double bst[3] = {1.0, 0.25, 2.0 / 3.0};
   for (int i = K - 1; i >= 0; --i) {
@@ -685,6 +687,10 @@ int hydro_set_option(hydro_ctx* ctx, int option, int value) {
       if (value != 0 && value != 1) return fail(ctx, HYDRO_EINVAL, "HYDRO_OPT_X_KERNEL takes 0 or 1");
       ctx->x_tile = value;
       return HYDRO_OK;
+    case HYDRO_OPT_ADJ_SKIP_N:
+      if (value != 0 && value != 1) return fail(ctx, HYDRO_EINVAL, "HYDRO_OPT_ADJ_SKIP_N takes 0 or 1");
+      ctx->adj_skip_n = value;
+      return HYDRO_OK;
     default:
       return fail(ctx, HYDRO_EINVAL, "unknown option");
   }
@@ -696,6 +702,7 @@ int hydro_get_option(hydro_ctx* ctx, int option, int* value) {
     case HYDRO_OPT_YZ_KERNEL: *value = ctx->yz_tile ? 0 : 1; return HYDRO_OK;
     case HYDRO_OPT_MARCH_SEG: *value = ctx->seg; return HYDRO_OK;
     case HYDRO_OPT_X_KERNEL: *value = ctx->x_tile; return HYDRO_OK;
+    case HYDRO_OPT_ADJ_SKIP_N: *value = ctx->adj_skip_n; return HYDRO_OK;
     default: return fail(ctx, HYDRO_EINVAL, "unknown option");
   }
 }

@@ -166,6 +166,10 @@ struct AdjArgs {
   R dt;
   R* acc;
   R* lW;
+  // 1: the N component of mu is taken as zero; N's reverse reconstructions are
+  // skipped and its outputs (G, lW, acc) are zero.  N enters no other field's
+  // flux and no source, so with a zero N adjoint on entry this is exact.
+  int skip_n;
 };
 
 // LDS of the line adjoint kernel, in elements of the field type: split fluxes

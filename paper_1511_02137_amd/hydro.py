@@ -31,7 +31,7 @@ EXPORTED = [
     "hydro_batch_sums", "hydro_batch_get_state", "hydro_batch_diag", "hydro_batch_last_error",
     "hydro_batch_destroy",
 ]
-OPT_YZ_KERNEL, OPT_MARCH_SEG, OPT_X_KERNEL = 0, 1, 2
+OPT_YZ_KERNEL, OPT_MARCH_SEG, OPT_X_KERNEL, OPT_ADJ_SKIP_N = 0, 1, 2, 3
 BOPT_BLOCKS_X, BOPT_BLOCKS_Y, BOPT_BLOCKS_Z, BOPT_GRAPH, BOPT_X_ROWS = 0, 1, 2, 3, 4
 KERNELS = ["xface", "xbound", "ymarch", "jet", "zmarch", "sums", "adjoint"]
 

@@ -311,3 +311,40 @@ def test_adjoint_step_dot_product_with_oracle_jvp(weno, bc):
         Vf[f] = V[f]
         _, JVf = O.jvp(pb, U0, Vf, steps, oracle_jets(w))
         assert abs(np.sum(lam0[f] * V[f]) - np.sum(Wt * JVf)) <= 1e-10 * scale, f
+
+
+def test_skip_n_option_is_exact_for_zero_n_adjoint():
+    """HYDRO_OPT_ADJ_SKIP_N: with lambda_N = 0 on entry the skipping sweep
+    returns the general sweep's result (values equal, N component zero); with
+    lambda_N != 0 it returns the general sweep of lambda with N zeroed."""
+    from paper_1511_02137_amd import hydro as H
+    steps = 2
+    w = small(n=(21, 18, 16), steps=steps)
+    pb = oracle_problem(w)
+    U0 = torch.tensor(O.prim_to_cons(pb, w.prim0), dtype=torch.float64, device="cuda")
+    Wt = np.stack([smooth_direction(pb.shape, 80 + f) for f in range(5)])
+    outs = {}
+    for skip in (0, 1):
+        for zero_n in (True, False):
+            h = H.from_workload(w, precision="f64", adjoint_k=steps)
+            h.set_option(H.OPT_ADJ_SKIP_N, skip)
+            assert h.get_option(H.OPT_ADJ_SKIP_N) == skip
+            lam = torch.tensor(Wt, dtype=torch.float64, device="cuda")
+            if zero_n:
+                lam[4] = 0
+            grad = torch.zeros((1, 5), dtype=torch.float64, device="cuda")
+            h.adjoint_step(U0, 0, [w.jets[0].E0], steps, lam, grad)
+            torch.cuda.synchronize()
+            outs[skip, zero_n] = (lam.cpu().numpy(), grad.cpu().numpy())
+            h.close()
+    for k in range(2):
+        assert np.array_equal(outs[1, True][k], outs[0, True][k])
+        assert np.array_equal(outs[1, False][k], outs[0, True][k])
+    assert not np.any(outs[1, True][0][4])
+    assert np.any(outs[0, False][0][4])
+    with pytest.raises(H.HydroError):
+        h = H.from_workload(w, precision="f64")
+        try:
+            h.set_option(H.OPT_ADJ_SKIP_N, 2)
+        finally:
+            h.close()
