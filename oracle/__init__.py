@@ -22,6 +22,10 @@ Parity status per function (pins in tests/test_oracle_*.py):
   eps2             pinned (closed form on a separable field)
   eps2_complex_step pinned (central finite differences of run)
   jvp              pinned (central finite differences of run)
+  limit_face, run with limiter="pp"
+                   pinned (admissibility invariant, brute-force largest
+                   theta, exact root for linear constraints, inactive on
+                   smooth flows, conservation, the LF premise u +- f(u))
 """
 from __future__ import annotations
 
@@ -50,6 +54,7 @@ class OCfg(ctypes.Structure):
         ("weno_eps", ctypes.c_double),
         ("eos_dof", ctypes.c_double),
         ("hbarc", ctypes.c_double),
+        ("limiter", ctypes.c_int32),
     ]
 
 
@@ -68,6 +73,7 @@ class OJet(ctypes.Structure):
 WENO = {"z": 0, "js": 1, "linear": 2, "z5": 3, "js5": 4, "linear5": 5}
 BC = {"outflow": 0, "periodic": 1}
 DEPOSIT = {"ngp": 0, "gauss": 1}
+LIMITER = {"none": 0, "pp": 1}
 
 
 def _load():
@@ -101,8 +107,9 @@ def _load():
     lib.oracle_eps2_complex_step.argtypes = [cp, jp, ctypes.c_int, dp, ctypes.c_int, ctypes.c_int,
                                              ctypes.c_int, ctypes.c_double, dp, dp, dp]
     lib.oracle_jvp.argtypes = [cp, jp, ctypes.c_int, dp, dp, ctypes.c_int, ctypes.c_double, dp, dp]
+    lib.oracle_limit_face.argtypes = [cp, ctypes.c_int, dp, dp, dp, dp]
     for name in ("oracle_prim_to_cons", "oracle_cons_to_prim", "oracle_rhs", "oracle_run",
-                 "oracle_sums", "oracle_eps2", "oracle_eps2_complex_step", "oracle_jvp"):
+                 "oracle_sums", "oracle_eps2", "oracle_eps2_complex_step", "oracle_jvp", "oracle_limit_face"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -127,6 +134,7 @@ class Problem:
     weno_eps: float = 1e-6
     eos_dof: float = 47.5
     hbarc: float = 0.1973269804
+    limiter: str = "none"
 
     def c(self) -> OCfg:
         c = OCfg()
@@ -141,6 +149,7 @@ class Problem:
         c.weno_eps = float(self.weno_eps)
         c.eos_dof = float(self.eos_dof)
         c.hbarc = float(self.hbarc)
+        c.limiter = LIMITER[self.limiter] if isinstance(self.limiter, str) else int(self.limiter)
         return c
 
     @property
@@ -316,3 +325,16 @@ def jvp(pb: Problem, U0: np.ndarray, V: np.ndarray, nsteps: int, jets=None, h: f
     rc = _load().oracle_jvp(ctypes.byref(c), arr, nj, _dp(U0), _dp(V), int(nsteps), float(h), _dp(Uo), _dp(JV))
     assert rc == 0
     return Uo, JV
+
+
+def limit_face(pb: Problem, d: int, uA, uB, H):
+    """The positivity-preserving limiter on one face along axis d (0 x, 1 y,
+    2 z) between conserved states uA (low side) and uB: (limited H, theta)."""
+    uA = np.ascontiguousarray(uA, dtype=np.float64)
+    uB = np.ascontiguousarray(uB, dtype=np.float64)
+    Hc = np.array(H, dtype=np.float64)
+    th = ctypes.c_double()
+    c = pb.c()
+    rc = _load().oracle_limit_face(ctypes.byref(c), int(d), _dp(uA), _dp(uB), _dp(Hc), ctypes.byref(th))
+    assert rc == 0
+    return Hc, th.value

@@ -74,6 +74,7 @@ typedef struct {
   double weno_eps;    // epsilon of the weights (1e-6)
   double eos_dof;     // g in e = g pi^2/30 T^4 / (hbar c)^3   (47.5)
   double hbarc;       // hbar c [GeV fm]                           (0.1973269804)
+  int32_t limiter;    // 0 = none, 1 = positivity-preserving flux limiter
 } ocfg;
 
 typedef struct {
@@ -391,21 +392,25 @@ struct Solver {
 #pragma omp parallel for collapse(2) schedule(static)
     for (int b = 0; b < n2; ++b) {
       for (int a = 0; a < n1; ++a) {
-        std::vector<S> Fp(n + 8), Fm(n + 8), Fh(n + 1);
+        std::vector<S> Fp(n + 8), Fm(n + 8), Fh(5 * (n + 1));
+        auto padded = [&](int P) {
+          int idx[3];
+          idx[d] = P;
+          idx[e1] = a + 4;
+          idx[e2] = b + 4;
+          return g.atp(idx[0], idx[1], idx[2]);
+        };
         for (int comp = 0; comp < 5; ++comp) {
           // split fluxes along the line, padded index P in [0, n+8)
           for (int P = 0; P < n + 8; ++P) {
-            int idx[3];
-            idx[d] = P;
-            idx[e1] = a + 4;
-            idx[e2] = b + 4;
-            size_t q = g.atp(idx[0], idx[1], idx[2]);
+            size_t q = padded(P);
             S f = flux(d, comp, q);
             S u = Wp[comp * np + q];
             Fp[P] = 0.5 * (f + u);  // Lax-Friedrichs splitting, alpha = 1
             Fm[P] = 0.5 * (f - u);
           }
-          // faces i+1/2 for i = -1..n-1 (Fh[i+1])
+          // faces i+1/2 for i = -1..n-1 (Fh[comp][i+1])
+          S* Fc = &Fh[comp * (n + 1)];
           for (int i = -1; i < n; ++i) {
             int P = i + 4;  // padded index of cell i
             if (c.weno >= 3) {  // 5th order: three ghost cells are used
@@ -414,7 +419,7 @@ struct Solver {
                 left[m] = Fp[P - 2 + m];    // F+ at i-2..i+2
                 right[m] = Fm[P + 3 - m];   // F- at i+3..i-1 (mirrored stencil)
               }
-              Fh[i + 1] = weno5_left(left, c.weno - 3, c.weno_eps, c.weno_p) +
+              Fc[i + 1] = weno5_left(left, c.weno - 3, c.weno_eps, c.weno_p) +
                           weno5_left(right, c.weno - 3, c.weno_eps, c.weno_p);
               continue;
             }
@@ -423,20 +428,96 @@ struct Solver {
               left[m] = Fp[P - 3 + m];    // F+ at i-3..i+3
               right[m] = Fm[P + 4 - m];   // F- at i+4..i-2 (mirrored stencil)
             }
-            Fh[i + 1] = weno7_left(left, c.weno, c.weno_eps, c.weno_p) +
+            Fc[i + 1] = weno7_left(left, c.weno, c.weno_eps, c.weno_p) +
                         weno7_left(right, c.weno, c.weno_eps, c.weno_p);
           }
+        }
+        if (c.limiter == 1) {
+          for (int i = -1; i < n; ++i) {
+            size_t qa = padded(i + 4), qb = padded(i + 5);
+            S uA[5], fA[5], uB[5], fB[5], H[5];
+            for (int comp = 0; comp < 5; ++comp) {
+              uA[comp] = Wp[comp * np + qa];
+              fA[comp] = flux(d, comp, qa);
+              uB[comp] = Wp[comp * np + qb];
+              fB[comp] = flux(d, comp, qb);
+              H[comp] = Fh[comp * (n + 1) + i + 1];
+            }
+            limit_face(uA, fA, uB, fB, H);
+            for (int comp = 0; comp < 5; ++comp) Fh[comp * (n + 1) + i + 1] = H[comp];
+          }
+        }
+        for (int comp = 0; comp < 5; ++comp) {
+          const S* Fc = &Fh[comp * (n + 1)];
           for (int i = 0; i < n; ++i) {
             int idx[3];
             idx[d] = i;
             idx[e1] = a;
             idx[e2] = b;
             size_t cell = g.at(idx[0], idx[1], idx[2]);
-            L[comp * nc + cell] = L[comp * nc + cell] + (-(Fh[i + 1] - Fh[i]) / dx);
+            L[comp * nc + cell] = L[comp * nc + cell] + (-(Fc[i + 1] - Fc[i]) / dx);
           }
         }
       }
     }
+  }
+
+  // Positivity-preserving flux limiter (after Zhang and Shu, the WENO
+  // reference of the paper).  A forward-Euler update of a cell,
+  //   u_i - sum_d lam_d (F_{d,i+1/2} - F_{d,i-1/2}),   lam_d = dt/dx_d,
+  // equals sum_d w_d (R_d + L_d)/2 with w_d = lam_d / sum lam and the two
+  // half states
+  //   R_d = u_i - mu (F_{d,i+1/2} - f_d(u_i)/2),  L_d = u_i + mu (F_{d,i-1/2} - f_d(u_i)/2),
+  // mu = 2 dt sum_d 1/dx_d.  With the first-order Lax-Friedrichs flux
+  // F = (f(u_i) + u_i)/2 + (f(u_{i+1}) - u_{i+1})/2 they are
+  //   R = (1 - mu/2) u_i + mu/2 (u_{i+1} - f(u_{i+1})),
+  //   L = (1 - mu/2) u_i + mu/2 (u_{i-1} + f(u_{i-1})),
+  // admissible for mu/2 <= 1 because u +- f(u) is (alpha = 1).  The face flux
+  // becomes theta F_high + (1 - theta) F_LF with the largest theta of the
+  // chord rule below that keeps both half states next to the face in
+  //   { E - |M| >= eps, N >= eps }  (convex: the first function is concave).
+  // The source adds (P, P dir) with |dir| = 1 and the RK3 stages are convex
+  // combinations, so whole steps stay in the set.
+  static constexpr double kPPEps = 1e-13;
+
+  // Largest theta in [0, 1] with h(theta) >= 0 given h concave on [0, 1]:
+  // 1 if h(1) >= 0, 0 if h(0) <= 0, else the chord's root h(0)/(h(0) - h(1))
+  // (concavity puts h above the chord).
+  static S chord_theta(const S& h0, const S& h1) {
+    if (re(h1) >= 0.0) return S(1.0);
+    if (re(h0) <= 0.0) return S(0.0);
+    return h0 / (h0 - h1);
+  }
+
+  // theta for one half state s(theta) = s0 + theta (s1 - s0).
+  static S side_theta(const S s0[5], const S s1[5]) {
+    S m0 = csqrt(s0[1] * s0[1] + s0[2] * s0[2] + s0[3] * s0[3]);
+    S m1 = csqrt(s1[1] * s1[1] + s1[2] * s1[2] + s1[3] * s1[3]);
+    S tq = chord_theta(s0[0] - m0 - kPPEps, s1[0] - m1 - kPPEps);
+    S tn = chord_theta(s0[4] - kPPEps, s1[4] - kPPEps);
+    return re(tn) < re(tq) ? tn : tq;
+  }
+
+  void limit_face(const S uA[5], const S fA[5], const S uB[5], const S fB[5], S H[5]) const {
+    const double mu = 2.0 * c.dt * (1.0 / c.dx[0] + 1.0 / c.dx[1] + 1.0 / c.dx[2]);
+    limit_face_mu(mu, uA, fA, uB, fB, H);
+  }
+
+  // Returns theta; H becomes theta H + (1 - theta) F_LF.
+  static S limit_face_mu(double mu, const S uA[5], const S fA[5], const S uB[5], const S fB[5], S H[5]) {
+    S FL[5], RA0[5], RA1[5], LB0[5], LB1[5];
+    for (int comp = 0; comp < 5; ++comp) {
+      FL[comp] = 0.5 * (fA[comp] + uA[comp]) + 0.5 * (fB[comp] - uB[comp]);
+      RA0[comp] = uA[comp] - mu * (FL[comp] - 0.5 * fA[comp]);
+      RA1[comp] = uA[comp] - mu * (H[comp] - 0.5 * fA[comp]);
+      LB0[comp] = uB[comp] + mu * (FL[comp] - 0.5 * fB[comp]);
+      LB1[comp] = uB[comp] + mu * (H[comp] - 0.5 * fB[comp]);
+    }
+    S ta = side_theta(RA0, RA1);
+    S tb = side_theta(LB0, LB1);
+    S th = re(tb) < re(ta) ? tb : ta;
+    for (int comp = 0; comp < 5; ++comp) H[comp] = th * H[comp] + (1.0 - th) * FL[comp];
+    return th;
   }
 
   S cell_temperature(int i, int j, int k) const {
@@ -637,6 +718,7 @@ bool valid(const ocfg* c) {
     if (c->bc[d] != 0 && c->bc[d] != 1) return false;
   }
   if (c->weno < 0 || c->weno > 5 || c->deposit < 0 || c->deposit > 1 || c->weno_p < 1) return false;
+  if (c->limiter < 0 || c->limiter > 1) return false;
   return c->dt > 0.0;
 }
 
@@ -802,6 +884,28 @@ int oracle_jvp(const ocfg* c, const ojet* jets, int njet, const double* U0, cons
     Uout[q] = U[q].real();
     JV[q] = U[q].imag() / h;
   }
+  return 0;
+}
+
+// The flux limiter on one face along axis d between the cells with conserved
+// states uA (low side) and uB (high side): H (five face fluxes) in/out,
+// *theta the limiter's weight of the high-order flux.
+int oracle_limit_face(const ocfg* c, int d, const double* uA, const double* uB, double* H, double* theta) {
+  if (!valid(c) || d < 0 || d > 2) return -1;
+  long long fx = 0;
+  double fA[5], fB[5];
+  const double* us[2] = {uA, uB};
+  double* fs[2] = {fA, fB};
+  for (int k = 0; k < 2; ++k) {
+    const double* u = us[k];
+    Prim<double> p = cons_to_prim(u[0], u[1], u[2], u[3], u[4], &fx);
+    const double pr = p.e / 3.0;
+    fs[k][0] = u[1 + d];
+    for (int m = 0; m < 3; ++m) fs[k][1 + m] = u[1 + m] * p.v[d] + (m == d ? pr : 0.0);
+    fs[k][4] = u[4] * p.v[d];
+  }
+  const double mu = 2.0 * c->dt * (1.0 / c->dx[0] + 1.0 / c->dx[1] + 1.0 / c->dx[2]);
+  *theta = Solver<double>::limit_face_mu(mu, uA, fA, uB, fB, H);
   return 0;
 }
 
