@@ -225,6 +225,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--yz", choices=["tile", "march"], default="tile", help="y/z face kernels")
     ap.add_argument("--x", choices=["row", "tile"], default="row", help="x face kernel")
+    ap.add_argument("--limiter", choices=["none", "pp"], default="none",
+                    help="face-flux limiter of the stage run (pp: positivity-preserving)")
     ap.add_argument("--weno", choices=sorted(RECON_FLOPS), default="z",
                     help="reconstruction: WENO7 (z, js, linear) or WENO5 (z5, js5, linear5)")
     ap.add_argument("--adjoint-n", type=int, default=128, help="grid edge of the differentiable run (0: skip)")
@@ -260,8 +262,8 @@ def main():
         return
 
     w = W.paper_event(2, n=(args.n,) * 3)
-    h = H.from_workload(w, precision=args.precision, weno=args.weno)
-    fpc = flops_per_cell(args.weno)
+    h = H.from_workload(w, precision=args.precision, weno=args.weno, limiter=args.limiter)
+    fpc = flops_per_cell(args.weno)  # the limiter's own arithmetic is not counted
     fpc_update = sum(fpc.values())
     h.set_option(H.OPT_YZ_KERNEL, 0 if args.yz == "tile" else 1)
     h.set_option(H.OPT_X_KERNEL, 0 if args.x == "row" else 1)
@@ -294,7 +296,8 @@ def main():
     achieved = fpc[dom] * nc / (t_launch * 1e-3) / 1e12
     peak = PEAK_TFLOPS[args.precision]
     traffic = None
-    rec = MEASURED_TRAFFIC.get((dom, args.precision, args.yz, args.n)) if args.weno == "z" else None
+    rec = (MEASURED_TRAFFIC.get((dom, args.precision, args.yz, args.n))
+           if args.weno == "z" and args.limiter == "none" else None)
     if rec is not None:
         import hashlib
         src = os.path.join(ROOT, "paper_1511_02137_amd", "csrc", "hydro_kernels.hip")
@@ -321,10 +324,12 @@ def main():
         "vs_baseline": None,
         "dtype": args.precision,
         "data": "synthetic",
-        "config": {"workload": "%s: %d^3 cells, dx 0.1 fm, dt 0.02 fm/c, p = e/3, %s + LF split, "
-                               "SSP-RK3, 1 jet (NGP), outflow" % (w.name, args.n, SCHEME_NAMES[args.weno]),
+        "config": {"workload": "%s: %d^3 cells, dx 0.1 fm, dt 0.02 fm/c, p = e/3, %s + LF split%s, "
+                               "SSP-RK3, 1 jet (NGP), outflow" % (w.name, args.n, SCHEME_NAMES[args.weno],
+                                                                  " + positivity limiter" if args.limiter == "pp"
+                                                                  else ""),
                    "grid": list(w.n), "precision": args.precision, "jets": len(w.jets), "yz_kernel": args.yz,
-                   "x_kernel": args.x, "weno": args.weno},
+                   "x_kernel": args.x, "weno": args.weno, "limiter": args.limiter},
         "roofline": roofline,
         "step_alu_frac": step_frac,
         "flops_per_cell_update": fpc_update,

@@ -79,6 +79,19 @@ typedef enum {
   HYDRO_WENO5_LINEAR = 5
 } hydro_weno;
 
+/* Face-flux limiter.  HYDRO_LIMITER_PP: the positivity-preserving flux
+ * limiter after Zhang and Shu (the WENO reference of the paper): each face
+ * flux F becomes theta F + (1 - theta) F_LF, F_LF = F+(u_i) + F-(u_{i+1})
+ * the first-order Lax-Friedrichs flux, theta in [0, 1] the largest value of
+ * a chord rule that keeps the half states u_i - mu (F - f(u_i)/2) and
+ * u_{i+1} + mu (F - f(u_{i+1})/2), mu = 2 dt sum_d 1/dx_d, inside
+ * { E - |M| >= 1e-13, N >= 1e-13 }.  For admissible input states and
+ * dt sum_d 1/dx_d <= 1 every stage output is then admissible (E > |M|,
+ * N > 0) up to rounding, with no recovery fix-ups.  Faces that need no
+ * limiting keep their WENO flux exactly.  FP64 arithmetic in both forms.
+ * hydro_adjoint_step does not support it (HYDRO_EINVAL). */
+typedef enum { HYDRO_LIMITER_NONE = 0, HYDRO_LIMITER_PP = 1 } hydro_limiter;
+
 typedef struct {
   int32_t n[3];        /* cells along x, y, z >= 1; n[0] <= 810 (FP64) or 1024 (FP32),
                           n[1], n[2] <= 65535 */
@@ -94,6 +107,7 @@ typedef struct {
   int32_t strict;      /* 1: hydro_sums reports HYDRO_ENONPHYS after fix-ups */
   double eos_dof;      /* g of e = g pi^2/30 T^4/(hbar c)^3; 47.5 */
   double hbarc;        /* hbar c [GeV fm]; 0.1973269804 */
+  int32_t limiter;     /* hydro_limiter (default HYDRO_LIMITER_NONE) */
 } hydro_config;
 
 /* One jet (Eq. 2, 3): a straight line at the speed of light from x0 in
@@ -115,7 +129,8 @@ typedef struct {
 typedef struct hydro_ctx hydro_ctx;
 
 /* Fill *cfg with the defaults: the paper's 256^3 shape, dx = 0.1 fm,
- * dt = 0.02 fm/c, t0 = 1 fm/c, outflow, FP64, WENO-Z, NGP deposit. */
+ * dt = 0.02 fm/c, t0 = 1 fm/c, outflow, FP64, WENO-Z, NGP deposit, no
+ * limiter. */
 void hydro_default_config(hydro_config* cfg);
 
 /* Bytes of caller-provided device workspace that hydro_init needs for cfg:

@@ -160,18 +160,20 @@ hipError_t stage_impl(hydro_ctx* ctx, const R* W, const R* Un, R* out, int stage
   a.Un = Un;
   a.out = out;
   a.D = static_cast<R*>(ctx->D);
+  a.pp_mu = pp_mu(c);
+  const int scheme = face_scheme(c);
   hipError_t e;
   {
     ProfScope p(ctx, HYDRO_K_XFACE, st);
-    e = launch_face_kernel<R>(ctx->x_tile ? 6 : 0, a, c.weno, ctx->seg, st);
+    e = launch_face_kernel<R>(ctx->x_tile ? 6 : 0, a, scheme, ctx->seg, st);
   }
   if (e == hipSuccess && c.bc[0] == HYDRO_BC_OUTFLOW && !ctx->x_tile) {
     ProfScope p(ctx, HYDRO_K_XBOUND, st);
-    e = launch_face_kernel<R>(1, a, c.weno, ctx->seg, st);
+    e = launch_face_kernel<R>(1, a, scheme, ctx->seg, st);
   }
   if (e == hipSuccess) {
     ProfScope p(ctx, HYDRO_K_YMARCH, st);
-    e = launch_face_kernel<R>(ctx->yz_tile ? 4 : 2, a, c.weno, ctx->seg, st);
+    e = launch_face_kernel<R>(ctx->yz_tile ? 4 : 2, a, scheme, ctx->seg, st);
   }
   if (e == hipSuccess && ctx->njet > 0) {
     JetArgs j;
@@ -191,7 +193,7 @@ hipError_t stage_impl(hydro_ctx* ctx, const R* W, const R* Un, R* out, int stage
   }
   if (e == hipSuccess) {
     ProfScope p(ctx, HYDRO_K_ZMARCH, st);
-    e = launch_face_kernel<R>(ctx->yz_tile ? 5 : 3, a, c.weno, ctx->seg, st);
+    e = launch_face_kernel<R>(ctx->yz_tile ? 5 : 3, a, scheme, ctx->seg, st);
   }
   return e;
 }
@@ -226,6 +228,10 @@ int step_impl(hydro_ctx* ctx, R* U, int nsteps, hipStream_t st) {
 bool adjoint_fits(const hydro_config* c, std::string* why) {
   if (c->weno > 2) {
     if (why) *why = "the adjoint is built for the WENO7 schemes only";
+    return false;
+  }
+  if (c->limiter != HYDRO_LIMITER_NONE) {
+    if (why) *why = "the adjoint is built without the flux limiter";
     return false;
   }
   for (int d = 0; d < 3; ++d) {
@@ -350,6 +356,7 @@ void hydro_default_config(hydro_config* c) {
   c->strict = 0;
   c->eos_dof = 47.5;
   c->hbarc = 0.1973269804;
+  c->limiter = HYDRO_LIMITER_NONE;
 }
 
 size_t hydro_workspace_bytes(const hydro_config* cfg, int adjoint_k) {

@@ -75,7 +75,8 @@ void drop_graph(hydro_batch* b) {
 }
 
 bool compatible(const hydro_config& a, const hydro_config& c) {
-  return a.precision == c.precision && a.weno == c.weno && a.weno_eps == c.weno_eps && a.weno_p == c.weno_p;
+  return a.precision == c.precision && a.weno == c.weno && a.weno_eps == c.weno_eps && a.weno_p == c.weno_p &&
+         a.limiter == c.limiter;
 }
 
 size_t field_bytes(const hydro_config& c) { return align256((size_t)5 * ncells(&c) * elem_size(&c)); }
@@ -99,7 +100,7 @@ BatchArgs<R> batch_args(const hydro_batch* b, int AX, int stage) {
 // y tiles, jets, z tiles (+ RK combine).
 template <class R>
 hipError_t stage_launches(hydro_batch* b, int stage, hipStream_t st) {
-  const int scheme = b->cfg[0].weno;
+  const int scheme = face_scheme(b->cfg[0]);
   hipError_t e;
   if (b->xrows) {
     e = launch_batch_axis<R>(3, batch_args<R>(b, 3, stage), scheme, b->blocks[0], st);
@@ -161,7 +162,7 @@ std::string tune_key(const hydro_batch* b) {
   int dev = 0;
   (void)hipGetDevice(&dev);
   if (hipGetDeviceProperties(&p, dev) == hipSuccess) k << p.gcnArchName << ":" << p.multiProcessorCount;
-  k << ":p" << b->cfg[0].precision << ":w" << b->cfg[0].weno;
+  k << ":p" << b->cfg[0].precision << ":w" << b->cfg[0].weno << ":l" << b->cfg[0].limiter;
   for (const auto& s : shapes) k << ":" << s;
   unsigned long long h = 1469598103934665603ULL;
   for (unsigned char ch : k.str()) {
@@ -212,7 +213,7 @@ hipError_t time_axis(hydro_batch* b, int AX, long long blocks, int reps, hipStre
   }
   std::vector<float> t;
   const BatchArgs<R> a = batch_args<R>(b, AX, 0);
-  const int scheme = b->cfg[0].weno;
+  const int scheme = face_scheme(b->cfg[0]);
   for (int r = 0; r <= reps && e == hipSuccess; ++r) {
     e = hipEventRecord(e0, st);
     if (e == hipSuccess) e = launch_batch_axis<R>(AX, a, scheme, blocks, st);
@@ -372,6 +373,7 @@ int hydro_batch_create(const hydro_config* cfgs, int n_events, const double* con
     v.dt = c.dt;
     for (int d = 0; d < 3; ++d) v.inv_d[d] = 1.0 / c.dx[d];
     v.dV = c.dx[0] * c.dx[1] * c.dx[2];
+    v.pp_mu = pp_mu(c);
     v.eos_dof = c.eos_dof;
     v.hbarc = c.hbarc;
     v.njet = 0;

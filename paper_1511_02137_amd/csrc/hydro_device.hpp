@@ -253,6 +253,77 @@ __device__ __forceinline__ R face_flux(const R* fp, const R* fm, R eps) {
          weno7<R, S>(fm[7], fm[6], fm[5], fm[4], fm[3], fm[2], fm[1], eps);
 }
 
+// ---------------------------------------------------------------------------
+// Positivity-preserving flux limiter (after Zhang and Shu).  Kernels take it
+// as the flag kPP on the scheme template argument.
+//
+// A forward-Euler update u_i - sum_d (dt/dx_d)(F_{d,i+1/2} - F_{d,i-1/2}) is
+// the mean over the axes, with weights (dt/dx_d) / sum(dt/dx), of the two
+// half states of each axis
+//   R = u_i - mu (F_{i+1/2} - f_i/2),   L = u_i + mu (F_{i-1/2} - f_i/2),
+// mu = 2 dt sum_d 1/dx_d.  For the first-order flux F+(u_i) + F-(u_{i+1})
+// they are (1 - mu/2) u_i + mu/2 (u_{i+1} - f_{i+1}) and (1 - mu/2) u_i +
+// mu/2 (u_{i-1} + f_{i-1}): admissible for mu/2 <= 1, since u +- f(u) is for
+// alpha = 1.  Each face flux F becomes theta F + (1 - theta) F_LF with the
+// largest theta of the chord rule (below) that keeps E - |M| >= kPPEps and
+// N >= kPPEps in the half state on each side of the face.  The split fluxes
+// of the two cells give u = F+ - F-, f = F+ + F- and F_LF = F+_i + F-_{i+1}.
+// FP64 in every form; a face that needs no limiting keeps its flux bit for bit.
+constexpr double kPPEps = 1e-13;
+
+__device__ __forceinline__ double pp_m2(const double s[5]) {
+  return fma(s[3], s[3], fma(s[2], s[2], s[1] * s[1]));
+}
+
+// E - |M| >= eps and N >= eps, without the square root.
+__device__ __forceinline__ bool pp_inside(const double s[5]) {
+  const double a = s[0] - kPPEps;
+  return a >= 0.0 && a * a >= pp_m2(s) && s[4] >= kPPEps;
+}
+
+// Largest theta in [0, 1] with h(theta) >= 0 for h concave: 1 if h(1) >= 0,
+// 0 if h(0) <= 0, else the root of the chord from (0, h0) to (1, h1), below
+// which h stays above the chord and so non-negative.
+__device__ __forceinline__ double pp_chord(double h0, double h1) {
+  if (h1 >= 0.0) return 1.0;
+  if (h0 <= 0.0) return 0.0;
+  return h0 / (h0 - h1);
+}
+
+__device__ __forceinline__ double pp_side(const double s0[5], const double s1[5]) {
+  const double tq = pp_chord(s0[0] - sqrt(pp_m2(s0)) - kPPEps, s1[0] - sqrt(pp_m2(s1)) - kPPEps);
+  const double tn = pp_chord(s0[4] - kPPEps, s1[4] - kPPEps);
+  return fmin(tq, tn);
+}
+
+// H: the face's five fluxes (in/out); pA/mA the split fluxes of the cell on
+// the low side of the face, pB/mB of the cell on the high side.
+template <class R>
+__device__ __forceinline__ void pp_limit(R H[5], const R pA[5], const R mA[5], const R pB[5], const R mB[5],
+                                         double mu) {
+  double ra[5], lb[5];
+#pragma unroll
+  for (int c = 0; c < 5; ++c) {
+    const double uA = (double)pA[c] - (double)mA[c], fA = (double)pA[c] + (double)mA[c];
+    const double uB = (double)pB[c] - (double)mB[c], fB = (double)pB[c] + (double)mB[c];
+    ra[c] = fma(-mu, fma(-0.5, fA, (double)H[c]), uA);
+    lb[c] = fma(mu, fma(-0.5, fB, (double)H[c]), uB);
+  }
+  if (pp_inside(ra) && pp_inside(lb)) return;
+  double ra0[5], lb0[5], fl[5];
+#pragma unroll
+  for (int c = 0; c < 5; ++c) {
+    const double uA = (double)pA[c] - (double)mA[c], fA = (double)pA[c] + (double)mA[c];
+    const double uB = (double)pB[c] - (double)mB[c], fB = (double)pB[c] + (double)mB[c];
+    fl[c] = (double)pA[c] + (double)mB[c];
+    ra0[c] = fma(-mu, fma(-0.5, fA, fl[c]), uA);
+    lb0[c] = fma(mu, fma(-0.5, fB, fl[c]), uB);
+  }
+  const double th = fmin(pp_side(ra0, ra), pp_side(lb0, lb));
+#pragma unroll
+  for (int c = 0; c < 5; ++c) H[c] = (R)fma(th, (double)H[c], (1.0 - th) * fl[c]);
+}
+
 __device__ __forceinline__ void add_fixups(unsigned long long* ctr, unsigned fix) {
   if (fix) atomicAdd(ctr, (unsigned long long)fix);
 }

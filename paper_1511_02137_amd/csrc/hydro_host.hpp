@@ -38,12 +38,20 @@ inline bool config_ok(const hydro_config* c, std::string* why) {
   if (!(c->dt > 0.0) || !std::isfinite(c->dt) || !std::isfinite(c->t0)) return fail("dt must be > 0");
   if (c->precision != HYDRO_F64 && c->precision != HYDRO_F32) return fail("bad precision");
   if (c->weno < 0 || c->weno > 5) return fail("bad weno");
+  if (c->limiter != HYDRO_LIMITER_NONE && c->limiter != HYDRO_LIMITER_PP) return fail("bad limiter");
   if (c->deposit != HYDRO_DEP_NGP && c->deposit != HYDRO_DEP_GAUSS) return fail("bad deposit");
   if (!(c->weno_eps > 0.0)) return fail("weno_eps must be > 0");
   if (c->weno_p != 2) return fail("only weno_p = 2 is built");
   if (!(c->eos_dof > 0.0) || !(c->hbarc > 0.0)) return fail("eos_dof and hbarc must be > 0");
   return true;
 }
+
+// Template scheme argument of the face kernels: the WENO scheme, plus kPP
+// with the positivity-preserving limiter.
+inline int face_scheme(const hydro_config& c) { return c.weno | (c.limiter == HYDRO_LIMITER_PP ? kPP : 0); }
+
+// Half-state factor of the positivity-preserving limiter: 2 dt sum_d 1/dx_d.
+inline double pp_mu(const hydro_config& c) { return 2.0 * c.dt * ((1.0 / c.dx[0] + 1.0 / c.dx[1]) + 1.0 / c.dx[2]); }
 
 inline Grid make_grid(const hydro_config* c) {
   Grid g;

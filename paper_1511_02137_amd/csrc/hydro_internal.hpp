@@ -15,6 +15,9 @@ constexpr int kSumBlocks = 1024;   // fixed number of reduction blocks (fixed or
 
 // WENO7 with Z, Jiang-Shu or linear weights; 3..5: the same for WENO5.
 enum Scheme { kWenoZ = 0, kWenoJS = 1, kWenoLinear = 2, kWeno5Z = 3, kWeno5JS = 4, kWeno5Linear = 5 };
+// Flag on the face kernels' scheme template argument: positivity-preserving
+// flux limiter on.
+constexpr int kPP = 8;
 
 // Grid of one event.
 struct Grid {
@@ -56,6 +59,7 @@ struct StageArgs {
   int stage;    // 1, 2, 3 (RK stage); 0: write L = D + S instead of combining
   int seg;      // march segment length (y/z kernels)
   unsigned long long* fixups;
+  double pp_mu;  // 2 dt sum_d 1/dx_d, the half-state factor of the positivity limiter
 };
 
 // Arguments of the jet kernel.
@@ -129,6 +133,7 @@ struct BatchEvent {
   double inv_d[3];    // 1/dx per axis
   double dV;
   double eos_dof, hbarc;
+  double pp_mu;       // 2 dt sum_d 1/dx_d (positivity limiter)
   int njet;
   int deposit;
 };

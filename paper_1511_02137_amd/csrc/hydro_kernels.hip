@@ -81,7 +81,18 @@ __device__ __forceinline__ void xrows_body(const StageArgs<R>& a, long long row0
   if (act) {
     // face x - 1/2: F+ at x-4..x+2 (slots x..x+6), F- at x-3..x+3 (slots x+1..x+7)
 #pragma unroll
-    for (int c = 0; c < 5; ++c) Fh[c] = face_flux<R, S>(sFp + c * P + x, sFm + c * P + x, a.eps);
+    for (int c = 0; c < 5; ++c) Fh[c] = face_flux<R, (S & 7)>(sFp + c * P + x, sFm + c * P + x, a.eps);
+    if constexpr ((S & kPP) != 0) {  // cells x - 1 and x: slots x + 3 and x + 4
+      R pA[5], mA[5], pB[5], mB[5];
+#pragma unroll
+      for (int c = 0; c < 5; ++c) {
+        pA[c] = sFp[c * P + x + 3];
+        mA[c] = sFm[c * P + x + 3];
+        pB[c] = sFp[c * P + x + 4];
+        mB[c] = sFm[c * P + x + 4];
+      }
+      pp_limit<R>(Fh, pA, mA, pB, mB, a.pp_mu);
+    }
   }
   __syncthreads();
   R* sF = s + (size_t)r * 5 * nx;  // [5][nx] per row
@@ -151,18 +162,36 @@ __device__ __forceinline__ void xbound_body(const StageArgs<R>& a, long long gro
     const long long row = group * kXBoundRows + l;
     if (row < rows) {
       sR[l][r] = (r & 1) == 0
-                     ? weno7<R, S>(sF[l][0][c], sF[l][1][c], sF[l][2][c], sF[l][3][c], sF[l][4][c], sF[l][5][c],
+                     ? weno7<R, (S & 7)>(sF[l][0][c], sF[l][1][c], sF[l][2][c], sF[l][3][c], sF[l][4][c], sF[l][5][c],
                                    sF[l][6][c], a.eps)
-                     : weno7<R, S>(sF[l][7][5 + c], sF[l][6][5 + c], sF[l][5][5 + c], sF[l][4][5 + c],
+                     : weno7<R, (S & 7)>(sF[l][7][5 + c], sF[l][6][5 + c], sF[l][5][5 + c], sF[l][4][5 + c],
                                    sF[l][3][5 + c], sF[l][2][5 + c], sF[l][1][5 + c], a.eps);
     }
   }
   __syncthreads();
+  if constexpr ((S & kPP) != 0) {  // one lane per row: cell nx-1 (point 3) and its copy (point 4)
+    if (t < kXBoundRows && group * kXBoundRows + t < rows) {
+      const int l = t;
+      R H[5], pA[5], mA[5], pB[5], mB[5];
+#pragma unroll
+      for (int c = 0; c < 5; ++c) {
+        H[c] = sR[l][2 * c] + sR[l][2 * c + 1];
+        pA[c] = sF[l][3][c];
+        mA[c] = sF[l][3][5 + c];
+        pB[c] = sF[l][4][c];
+        mB[c] = sF[l][4][5 + c];
+      }
+      pp_limit<R>(H, pA, mA, pB, mB, a.pp_mu);
+#pragma unroll
+      for (int c = 0; c < 5; ++c) sF[l][0][c] = H[c];  // point 0 is no longer read
+    }
+    __syncthreads();
+  }
   if (t < kXBoundRows * 5) {
     const int l = t / 5, c = t % 5;
     const long long row = group * kXBoundRows + l;
     if (row < rows) {
-      const R r = sR[l][2 * c] + sR[l][2 * c + 1];
+      const R r = ((S & kPP) != 0) ? sF[l][0][c] : sR[l][2 * c] + sR[l][2 * c + 1];
       R* d = a.D + c * nc + row * nx + nx - 1;
       *d = (*d - r) * a.inv_d;
     }
@@ -179,6 +208,20 @@ __global__ void __launch_bounds__(kXBoundRows * 10) k_xbound(StageArgs<R> a) {
 // March along axis AX (1 = y, 2 = z).  blockDim = (64, BY): lanes along x,
 // threadIdx.y over the other transverse axis; blockIdx.z = segment of `seg`
 // cells along AX.  LAST: z-march, which finishes L and does the RK combine.
+// The limiter on the march's window: the face between window points 3 and 4.
+template <class R>
+__device__ __forceinline__ void march_limit(R H[5], const R (&fp)[5][8], const R (&fm)[5][8], double mu) {
+  R pA[5], mA[5], pB[5], mB[5];
+#pragma unroll
+  for (int c = 0; c < 5; ++c) {
+    pA[c] = fp[c][3];
+    mA[c] = fm[c][3];
+    pB[c] = fp[c][4];
+    mB[c] = fm[c][4];
+  }
+  pp_limit<R>(H, pA, mA, pB, mB, mu);
+}
+
 template <class R, int S, int AX, bool LAST>
 __global__ void __launch_bounds__(256) k_march(StageArgs<R> a) {
   const int nx = a.g.n[0], ny = a.g.n[1], nz = a.g.n[2];
@@ -211,7 +254,8 @@ __global__ void __launch_bounds__(256) k_march(StageArgs<R> a) {
   }
   R prev[5];
 #pragma unroll
-  for (int c = 0; c < 5; ++c) prev[c] = face_flux<R, S>(fp[c], fm[c], a.eps);
+  for (int c = 0; c < 5; ++c) prev[c] = face_flux<R, (S & 7)>(fp[c], fm[c], a.eps);
+  if constexpr ((S & kPP) != 0) march_limit<R>(prev, fp, fm, a.pp_mu);
 
   for (int i = i0; i < i1; ++i) {
 #pragma unroll
@@ -235,11 +279,14 @@ __global__ void __launch_bounds__(256) k_march(StageArgs<R> a) {
       }
     }
     const long long cell = base + (long long)i * stride;
+    R fh[5];
+#pragma unroll
+    for (int c = 0; c < 5; ++c) fh[c] = face_flux<R, (S & 7)>(fp[c], fm[c], a.eps);
+    if constexpr ((S & kPP) != 0) march_limit<R>(fh, fp, fm, a.pp_mu);
 #pragma unroll
     for (int c = 0; c < 5; ++c) {
-      const R fh = face_flux<R, S>(fp[c], fm[c], a.eps);
-      const R div = (prev[c] - fh) * a.inv_d;
-      prev[c] = fh;
+      const R div = (prev[c] - fh[c]) * a.inv_d;
+      prev[c] = fh[c];
       R* d = a.D + c * nc + cell;
       if (!LAST) {
         *d = *d + div;
@@ -278,6 +325,21 @@ constexpr int kTileXP = kTileX;      // x pitch of the LDS arrays (128-byte rows
 // Tile length along the axis: 31 cells (32 face rows, one face per lane)
 // or 32 cells (33 face rows, the last one by 16 lanes); the launchers pick
 // the one that wastes less for the axis length (tile_len).
+// The limiter on an LDS tile laid out [c][slot][pitch]: face row f lies
+// between the points in slots f + 3 and f + 4, column col.
+template <class R, int kP, int kPitch>
+__device__ __forceinline__ void tile_limit(R H[5], const R* sFp, const R* sFm, int f, int col, double mu) {
+  R pA[5], mA[5], pB[5], mB[5];
+#pragma unroll
+  for (int c = 0; c < 5; ++c) {
+    pA[c] = sFp[(c * kP + f + 3) * kPitch + col];
+    mA[c] = sFm[(c * kP + f + 3) * kPitch + col];
+    pB[c] = sFp[(c * kP + f + 4) * kPitch + col];
+    mB[c] = sFm[(c * kP + f + 4) * kPitch + col];
+  }
+  pp_limit<R>(H, pA, mA, pB, mB, mu);
+}
+
 template <class R, int S, int AX, bool LAST, int kTileA>
 __device__ __forceinline__ void tile_body(const StageArgs<R>& a, int bx, int by, int bz, R* s) {
   constexpr int kTileP = kTileA + 8;  // points along AX
@@ -355,9 +417,9 @@ __device__ __forceinline__ void tile_body(const StageArgs<R>& a, int bx, int by,
     for (int c = 0; c < 5; ++c) {
       const R* fp = sFp + (c * kTileP + ta) * kTileXP + tx;
       const R* fm = sFm + (c * kTileP + ta) * kTileXP + tx;
-      Fh[c] = weno7<R, S>(fp[0], fp[kTileXP], fp[2 * kTileXP], fp[3 * kTileXP], fp[4 * kTileXP], fp[5 * kTileXP],
+      Fh[c] = weno7<R, (S & 7)>(fp[0], fp[kTileXP], fp[2 * kTileXP], fp[3 * kTileXP], fp[4 * kTileXP], fp[5 * kTileXP],
                           fp[6 * kTileXP], a.eps) +
-              weno7<R, S>(fm[7 * kTileXP], fm[6 * kTileXP], fm[5 * kTileXP], fm[4 * kTileXP], fm[3 * kTileXP],
+              weno7<R, (S & 7)>(fm[7 * kTileXP], fm[6 * kTileXP], fm[5 * kTileXP], fm[4 * kTileXP], fm[3 * kTileXP],
                           fm[2 * kTileXP], fm[kTileXP], a.eps);
     }
   }
@@ -366,11 +428,15 @@ __device__ __forceinline__ void tile_body(const StageArgs<R>& a, int bx, int by,
     for (int c = 0; c < 5; ++c) {
       const R* fp = sFp + (c * kTileP + kTileA) * kTileXP + tx;
       const R* fm = sFm + (c * kTileP + kTileA) * kTileXP + tx;
-      Fh2[c] = weno7<R, S>(fp[0], fp[kTileXP], fp[2 * kTileXP], fp[3 * kTileXP], fp[4 * kTileXP], fp[5 * kTileXP],
+      Fh2[c] = weno7<R, (S & 7)>(fp[0], fp[kTileXP], fp[2 * kTileXP], fp[3 * kTileXP], fp[4 * kTileXP], fp[5 * kTileXP],
                            fp[6 * kTileXP], a.eps) +
-               weno7<R, S>(fm[7 * kTileXP], fm[6 * kTileXP], fm[5 * kTileXP], fm[4 * kTileXP], fm[3 * kTileXP],
+               weno7<R, (S & 7)>(fm[7 * kTileXP], fm[6 * kTileXP], fm[5 * kTileXP], fm[4 * kTileXP], fm[3 * kTileXP],
                            fm[2 * kTileXP], fm[kTileXP], a.eps);
     }
+  }
+  if constexpr ((S & kPP) != 0) {  // face row f: cells at slots f + 3 and f + 4
+    if (has1) tile_limit<R, kTileP, kTileXP>(Fh, sFp, sFm, ta, tx, a.pp_mu);
+    if (has2) tile_limit<R, kTileP, kTileXP>(Fh2, sFp, sFm, kTileA, tx, a.pp_mu);
   }
   __syncthreads();
   R* sF = s;  // [5][kTileA + 1][kTileXP]
@@ -472,9 +538,9 @@ __device__ __forceinline__ void xtile_body(const StageArgs<R>& a, int bx, int by
     for (int c = 0; c < 5; ++c) {
       const R* fp = sFp + (c * kXTileP + f) * kXTileY + r;
       const R* fm = sFm + (c * kXTileP + f) * kXTileY + r;
-      Fh[c] = weno7<R, S>(fp[0], fp[kXTileY], fp[2 * kXTileY], fp[3 * kXTileY], fp[4 * kXTileY], fp[5 * kXTileY],
+      Fh[c] = weno7<R, (S & 7)>(fp[0], fp[kXTileY], fp[2 * kXTileY], fp[3 * kXTileY], fp[4 * kXTileY], fp[5 * kXTileY],
                           fp[6 * kXTileY], a.eps) +
-              weno7<R, S>(fm[7 * kXTileY], fm[6 * kXTileY], fm[5 * kXTileY], fm[4 * kXTileY], fm[3 * kXTileY],
+              weno7<R, (S & 7)>(fm[7 * kXTileY], fm[6 * kXTileY], fm[5 * kXTileY], fm[4 * kXTileY], fm[3 * kXTileY],
                           fm[2 * kXTileY], fm[kXTileY], a.eps);
     }
   }
@@ -483,11 +549,15 @@ __device__ __forceinline__ void xtile_body(const StageArgs<R>& a, int bx, int by
     for (int c = 0; c < 5; ++c) {
       const R* fp = sFp + (c * kXTileP + kXTileX) * kXTileY + r;
       const R* fm = sFm + (c * kXTileP + kXTileX) * kXTileY + r;
-      Fh2[c] = weno7<R, S>(fp[0], fp[kXTileY], fp[2 * kXTileY], fp[3 * kXTileY], fp[4 * kXTileY], fp[5 * kXTileY],
+      Fh2[c] = weno7<R, (S & 7)>(fp[0], fp[kXTileY], fp[2 * kXTileY], fp[3 * kXTileY], fp[4 * kXTileY], fp[5 * kXTileY],
                            fp[6 * kXTileY], a.eps) +
-               weno7<R, S>(fm[7 * kXTileY], fm[6 * kXTileY], fm[5 * kXTileY], fm[4 * kXTileY], fm[3 * kXTileY],
+               weno7<R, (S & 7)>(fm[7 * kXTileY], fm[6 * kXTileY], fm[5 * kXTileY], fm[4 * kXTileY], fm[3 * kXTileY],
                            fm[2 * kXTileY], fm[kXTileY], a.eps);
     }
+  }
+  if constexpr ((S & kPP) != 0) {  // face row f: cells at slots f + 3 and f + 4
+    if (has1) tile_limit<R, kXTileP, kXTileY>(Fh, sFp, sFm, f, r, a.pp_mu);
+    if (has2) tile_limit<R, kXTileP, kXTileY>(Fh2, sFp, sFm, kXTileX, r, a.pp_mu);
   }
   __syncthreads();
   R* sF = s;  // [5][kXTileX + 1][kXFacePitch]
@@ -755,6 +825,7 @@ __device__ __forceinline__ StageArgs<R> batch_stage_args(const BatchEvent& ev, i
   a.stage = stage;
   a.seg = 0;
   a.fixups = &ev.dev->fixups;
+  a.pp_mu = ev.pp_mu;
   return a;
 }
 
@@ -943,6 +1014,12 @@ hipError_t launch_face_kernel(int kernel, const StageArgs<R>& a, int scheme, int
     case kWeno5Z: HYDRO_DISPATCH(kWeno5Z) break;
     case kWeno5JS: HYDRO_DISPATCH(kWeno5JS) break;
     case kWeno5Linear: HYDRO_DISPATCH(kWeno5Linear) break;
+    case kWenoZ | kPP: HYDRO_DISPATCH(kWenoZ | kPP) break;
+    case kWenoJS | kPP: HYDRO_DISPATCH(kWenoJS | kPP) break;
+    case kWenoLinear | kPP: HYDRO_DISPATCH(kWenoLinear | kPP) break;
+    case kWeno5Z | kPP: HYDRO_DISPATCH(kWeno5Z | kPP) break;
+    case kWeno5JS | kPP: HYDRO_DISPATCH(kWeno5JS | kPP) break;
+    case kWeno5Linear | kPP: HYDRO_DISPATCH(kWeno5Linear | kPP) break;
     default: HYDRO_DISPATCH(kWenoZ) break;
   }
 #undef HYDRO_DISPATCH
@@ -1025,6 +1102,12 @@ hipError_t launch_batch_axis(int AX, const BatchArgs<R>& b, int scheme, long lon
     case kWeno5Z: HYDRO_BAXIS(kWeno5Z) break;
     case kWeno5JS: HYDRO_BAXIS(kWeno5JS) break;
     case kWeno5Linear: HYDRO_BAXIS(kWeno5Linear) break;
+    case kWenoZ | kPP: HYDRO_BAXIS(kWenoZ | kPP) break;
+    case kWenoJS | kPP: HYDRO_BAXIS(kWenoJS | kPP) break;
+    case kWenoLinear | kPP: HYDRO_BAXIS(kWenoLinear | kPP) break;
+    case kWeno5Z | kPP: HYDRO_BAXIS(kWeno5Z | kPP) break;
+    case kWeno5JS | kPP: HYDRO_BAXIS(kWeno5JS | kPP) break;
+    case kWeno5Linear | kPP: HYDRO_BAXIS(kWeno5Linear | kPP) break;
     default: HYDRO_BAXIS(kWenoZ) break;
   }
 #undef HYDRO_BAXIS

@@ -20,6 +20,7 @@ F64, F32 = 0, 1
 BC = {"outflow": 0, "periodic": 1}
 WENO = {"z": 0, "js": 1, "linear": 2, "z5": 3, "js5": 4, "linear5": 5}
 DEPOSIT = {"ngp": 0, "gauss": 1}
+LIMITER = {"none": 0, "pp": 1}
 
 EXPORTED = [
     "hydro_default_config", "hydro_workspace_bytes", "hydro_init", "hydro_add_jet", "hydro_rk3_step",
@@ -57,6 +58,7 @@ class Config(ctypes.Structure):
         ("strict", ctypes.c_int32),
         ("eos_dof", ctypes.c_double),
         ("hbarc", ctypes.c_double),
+        ("limiter", ctypes.c_int32),
     ]
 
 
@@ -141,7 +143,8 @@ def load_library(path: str = LIB_PATH):
 
 
 def make_config(n, dx=(0.1, 0.1, 0.1), dt=0.02, t0=1.0, bc=("outflow",) * 3, precision="f64", weno="z",
-                deposit="ngp", weno_eps=1e-6, strict=False, eos_dof=47.5, hbarc=0.1973269804) -> Config:
+                deposit="ngp", weno_eps=1e-6, strict=False, eos_dof=47.5, hbarc=0.1973269804,
+                limiter="none") -> Config:
     lib = load_library()
     c = Config()
     lib.hydro_default_config(ctypes.byref(c))
@@ -156,6 +159,7 @@ def make_config(n, dx=(0.1, 0.1, 0.1), dt=0.02, t0=1.0, bc=("outflow",) * 3, pre
     c.weno_eps = float(weno_eps)
     c.strict = 1 if strict else 0
     c.eos_dof, c.hbarc = float(eos_dof), float(hbarc)
+    c.limiter = LIMITER[limiter] if isinstance(limiter, str) else int(limiter)
     return c
 
 
@@ -355,9 +359,10 @@ class Hydro:
             pass
 
 
-def from_workload(w, precision: str = "f64", weno: str = "z", bc=None, adjoint_k: int = 0, device="cuda") -> Hydro:
+def from_workload(w, precision: str = "f64", weno: str = "z", bc=None, adjoint_k: int = 0, device="cuda",
+                  limiter: str = "none") -> Hydro:
     """Hydro for a paper_1511_02137_amd.workloads.Workload, with its jets."""
-    cfg = make_config(w.n, w.dx, w.dt, w.t0, bc or w.bc, precision, weno, w.deposit)
+    cfg = make_config(w.n, w.dx, w.dt, w.t0, bc or w.bc, precision, weno, w.deposit, limiter=limiter)
     h = Hydro(cfg, w.prim0, device=device, adjoint_k=adjoint_k)
     for j in w.jets:
         h.add_jet(j.x0, j.dir, j.E0, j.t_start, j.kappa_rad, j.kappa_coll, j.cr_over_cf)
@@ -476,9 +481,9 @@ class Batch:
             pass
 
 
-def batch_from_workloads(ws, precision: str = "f32", weno: str = "z", device="cuda") -> Batch:
+def batch_from_workloads(ws, precision: str = "f32", weno: str = "z", device="cuda", limiter: str = "none") -> Batch:
     """Batch of workloads.Workload events, with their jets."""
-    cfgs = [make_config(w.n, w.dx, w.dt, w.t0, w.bc, precision, weno, w.deposit) for w in ws]
+    cfgs = [make_config(w.n, w.dx, w.dt, w.t0, w.bc, precision, weno, w.deposit, limiter=limiter) for w in ws]
     b = Batch(cfgs, [w.prim0 for w in ws], device=device)
     for e, w in enumerate(ws):
         for j in w.jets:

@@ -194,3 +194,46 @@ def uniform_prim(n, e=3.0, v=(0.3, -0.2, 0.1), nn=0.7) -> np.ndarray:
     prim = np.empty((5, nz, ny, nx))
     prim[0], prim[1], prim[2], prim[3], prim[4] = e, v[0], v[1], v[2], nn
     return prim
+
+
+def peripheral_jet_event(n=(24, 20, 22), steps: int = 30, mirror: bool = False) -> Workload:
+    """A 92 GeV jet crossing the dilute edge of a small fireball (widths 0.2 of
+    the box, e0 = 27 GeV/fm^3, background 1e-3) with an NGP deposit: the kind
+    of event in which the unlimited WENO scheme leaves E < |M| behind the
+    deposit.  The origin sits off the cell faces; mirror=True gives the x ->
+    -x mirror image."""
+    dx = (0.1, 0.1, 0.1)
+    L = [n[k] * dx[k] for k in range(3)]
+    prim = ellipsoid_prim(n, dx, tuple(0.2 * x for x in L), 27.0)
+    d = (-0.9916173911378503, 0.02872803653083503, 0.12597479712246648)
+    x0 = (0.25 * L[0] + 0.0137, -L[0] / 3.2, -1.2 * L[0] / 3.2)
+    if mirror:
+        prim = prim[:, :, :, ::-1].copy()
+        prim[1] = -prim[1]
+        d = (-d[0], d[1], d[2])
+        x0 = (-x0[0], x0[1], x0[2])
+    jets = [JetSpec(x0=x0, dir=d, E0=92.3)]
+    return Workload("peripheral_jet_%dx%dx%d" % tuple(n), tuple(n), dx, 0.02, 1.0, steps, prim0=prim, jets=jets,
+                    e0=27.0)
+
+
+def vacuum_riemann(N: int = 200, e_right: float = 1e-8, axis: int = 0, ntrans: int = 4) -> Workload:
+    """Riemann problem of a fluid at rest, e = 10 | e_right (GeV/fm^3), charge
+    n = 1 | (e_right/10)^(3/4), on [-1, 1] fm along `axis` (outflow), ntrans
+    periodic cells across; dt = 0.2 dx, t = 0 -> 0.4 fm/c."""
+    dx = [1.0, 1.0, 1.0]
+    dx[axis] = 2.0 / N
+    n = [ntrans, ntrans, ntrans]
+    n[axis] = N
+    bc = ["periodic"] * 3
+    bc[axis] = "outflow"
+    dt = 0.2 * dx[axis]
+    x = centres(N, dx[axis])
+    shape = [1, 1, 1]
+    shape[2 - axis] = N
+    left = (x < 0).reshape(shape)
+    prim = np.zeros((5, n[2], n[1], n[0]))
+    prim[0] = np.where(left, 10.0, e_right)
+    prim[4] = np.where(left, 1.0, (e_right / 10.0) ** 0.75)
+    return Workload("vacuum_riemann_%d_axis%d" % (N, axis), tuple(n), tuple(dx), dt, 0.0, int(round(0.4 / dt)),
+                    bc=tuple(bc), prim0=prim, jets=[])
