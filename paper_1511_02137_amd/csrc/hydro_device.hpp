@@ -271,16 +271,6 @@ __device__ __forceinline__ R face_flux(const R* fp, const R* fm, R eps) {
 // FP64 in every form; a face that needs no limiting keeps its flux bit for bit.
 constexpr double kPPEps = 1e-13;
 
-__device__ __forceinline__ double pp_m2(const double s[5]) {
-  return fma(s[3], s[3], fma(s[2], s[2], s[1] * s[1]));
-}
-
-// E - |M| >= eps and N >= eps, without the square root.
-__device__ __forceinline__ bool pp_inside(const double s[5]) {
-  const double a = s[0] - kPPEps;
-  return a >= 0.0 && a * a >= pp_m2(s) && s[4] >= kPPEps;
-}
-
 // Largest theta in [0, 1] with h(theta) >= 0 for h concave: 1 if h(1) >= 0,
 // 0 if h(0) <= 0, else the root of the chord from (0, h0) to (1, h1), below
 // which h stays above the chord and so non-negative.
@@ -290,38 +280,60 @@ __device__ __forceinline__ double pp_chord(double h0, double h1) {
   return h0 / (h0 - h1);
 }
 
-__device__ __forceinline__ double pp_side(const double s0[5], const double s1[5]) {
-  const double tq = pp_chord(s0[0] - sqrt(pp_m2(s0)) - kPPEps, s1[0] - sqrt(pp_m2(s1)) - kPPEps);
-  const double tn = pp_chord(s0[4] - kPPEps, s1[4] - kPPEps);
+// E - |M| >= eps and N >= eps for E, |M|^2, N, without the square root.
+__device__ __forceinline__ bool pp_inside(double E, double m2, double N) {
+  const double a = E - kPPEps;
+  return a >= 0.0 && a * a >= m2 && N >= kPPEps;
+}
+
+// E, |M|^2 and N of a half state next to a face (side 0: the low cell's
+// u - mu (F - f/2), side 1: the high cell's u + mu (F - f/2)) for the face flux
+// F_c = H_c, or (lf) the first-order flux F+_low + F-_high.
+struct PPHalf {
+  double e, m2, n;
+};
+
+template <class R, class Get>
+__device__ __forceinline__ PPHalf pp_half(const R H[5], Get get, double mu, int side, bool lf) {
+  PPHalf r = {0.0, 0.0, 0.0};
+#pragma unroll
+  for (int c = 0; c < 5; ++c) {
+    const double p = (double)get(c, 2 * side), m = (double)get(c, 2 * side + 1);
+    const double F = lf ? (double)get(c, 0) + (double)get(c, 3) : (double)H[c];
+    const double hs = side ? fma(mu, fma(-0.5, p + m, F), p - m) : fma(-mu, fma(-0.5, p + m, F), p - m);
+    if (c == 0) r.e = hs;
+    else if (c == 4) r.n = hs;
+    else r.m2 = fma(hs, hs, r.m2);
+  }
+  return r;
+}
+
+// theta of one side from its half states with the first-order flux (s0) and
+// with H (s1).
+__device__ __forceinline__ double pp_side(const PPHalf& s0, const PPHalf& s1) {
+  const double tq = pp_chord(s0.e - sqrt(s0.m2) - kPPEps, s1.e - sqrt(s1.m2) - kPPEps);
+  const double tn = pp_chord(s0.n - kPPEps, s1.n - kPPEps);
   return fmin(tq, tn);
 }
 
-// H: the face's five fluxes (in/out); pA/mA the split fluxes of the cell on
-// the low side of the face, pB/mB of the cell on the high side.
-template <class R>
-__device__ __forceinline__ void pp_limit(R H[5], const R pA[5], const R mA[5], const R pB[5], const R mB[5],
-                                         double mu) {
-  double ra[5], lb[5];
+// H: the face's five fluxes (in/out).  get(c, k) returns component c of the
+// split fluxes of the two cells next to the face: k = 0 F+ and 1 F- of the
+// cell on the low side, 2 F+ and 3 F- of the cell on the high side.  Half
+// states are folded into E, |M|^2 and N component by component and one side
+// at a time, so that few values stay live.
+template <class R, class Get>
+__device__ __forceinline__ void pp_limit(R H[5], Get get, double mu) {
+  const PPHalf a1 = pp_half<R>(H, get, mu, 0, false);
+  const PPHalf b1 = pp_half<R>(H, get, mu, 1, false);
+  if (pp_inside(a1.e, a1.m2, a1.n) && pp_inside(b1.e, b1.m2, b1.n)) return;
+  const double ta = pp_side(pp_half<R>(H, get, mu, 0, true), a1);
+  const double tb = pp_side(pp_half<R>(H, get, mu, 1, true), b1);
+  const double th = fmin(ta, tb);
 #pragma unroll
   for (int c = 0; c < 5; ++c) {
-    const double uA = (double)pA[c] - (double)mA[c], fA = (double)pA[c] + (double)mA[c];
-    const double uB = (double)pB[c] - (double)mB[c], fB = (double)pB[c] + (double)mB[c];
-    ra[c] = fma(-mu, fma(-0.5, fA, (double)H[c]), uA);
-    lb[c] = fma(mu, fma(-0.5, fB, (double)H[c]), uB);
+    const double fl = (double)get(c, 0) + (double)get(c, 3);
+    H[c] = (R)fma(th, (double)H[c], (1.0 - th) * fl);
   }
-  if (pp_inside(ra) && pp_inside(lb)) return;
-  double ra0[5], lb0[5], fl[5];
-#pragma unroll
-  for (int c = 0; c < 5; ++c) {
-    const double uA = (double)pA[c] - (double)mA[c], fA = (double)pA[c] + (double)mA[c];
-    const double uB = (double)pB[c] - (double)mB[c], fB = (double)pB[c] + (double)mB[c];
-    fl[c] = (double)pA[c] + (double)mB[c];
-    ra0[c] = fma(-mu, fma(-0.5, fA, fl[c]), uA);
-    lb0[c] = fma(mu, fma(-0.5, fB, fl[c]), uB);
-  }
-  const double th = fmin(pp_side(ra0, ra), pp_side(lb0, lb));
-#pragma unroll
-  for (int c = 0; c < 5; ++c) H[c] = (R)fma(th, (double)H[c], (1.0 - th) * fl[c]);
 }
 
 __device__ __forceinline__ void add_fixups(unsigned long long* ctr, unsigned fix) {

@@ -83,15 +83,8 @@ __device__ __forceinline__ void xrows_body(const StageArgs<R>& a, long long row0
 #pragma unroll
     for (int c = 0; c < 5; ++c) Fh[c] = face_flux<R, (S & 7)>(sFp + c * P + x, sFm + c * P + x, a.eps);
     if constexpr ((S & kPP) != 0) {  // cells x - 1 and x: slots x + 3 and x + 4
-      R pA[5], mA[5], pB[5], mB[5];
-#pragma unroll
-      for (int c = 0; c < 5; ++c) {
-        pA[c] = sFp[c * P + x + 3];
-        mA[c] = sFm[c * P + x + 3];
-        pB[c] = sFp[c * P + x + 4];
-        mB[c] = sFm[c * P + x + 4];
-      }
-      pp_limit<R>(Fh, pA, mA, pB, mB, a.pp_mu);
+      pp_limit<R>(
+          Fh, [&](int c, int k) { return ((k & 1) ? sFm : sFp)[c * P + x + 3 + (k >> 1)]; }, a.pp_mu);
     }
   }
   __syncthreads();
@@ -172,16 +165,10 @@ __device__ __forceinline__ void xbound_body(const StageArgs<R>& a, long long gro
   if constexpr ((S & kPP) != 0) {  // one lane per row: cell nx-1 (point 3) and its copy (point 4)
     if (t < kXBoundRows && group * kXBoundRows + t < rows) {
       const int l = t;
-      R H[5], pA[5], mA[5], pB[5], mB[5];
+      R H[5];
 #pragma unroll
-      for (int c = 0; c < 5; ++c) {
-        H[c] = sR[l][2 * c] + sR[l][2 * c + 1];
-        pA[c] = sF[l][3][c];
-        mA[c] = sF[l][3][5 + c];
-        pB[c] = sF[l][4][c];
-        mB[c] = sF[l][4][5 + c];
-      }
-      pp_limit<R>(H, pA, mA, pB, mB, a.pp_mu);
+      for (int c = 0; c < 5; ++c) H[c] = sR[l][2 * c] + sR[l][2 * c + 1];
+      pp_limit<R>(H, [&](int c, int k) { return sF[l][3 + (k >> 1)][(k & 1) * 5 + c]; }, a.pp_mu);
 #pragma unroll
       for (int c = 0; c < 5; ++c) sF[l][0][c] = H[c];  // point 0 is no longer read
     }
@@ -211,15 +198,7 @@ __global__ void __launch_bounds__(kXBoundRows * 10) k_xbound(StageArgs<R> a) {
 // The limiter on the march's window: the face between window points 3 and 4.
 template <class R>
 __device__ __forceinline__ void march_limit(R H[5], const R (&fp)[5][8], const R (&fm)[5][8], double mu) {
-  R pA[5], mA[5], pB[5], mB[5];
-#pragma unroll
-  for (int c = 0; c < 5; ++c) {
-    pA[c] = fp[c][3];
-    mA[c] = fm[c][3];
-    pB[c] = fp[c][4];
-    mB[c] = fm[c][4];
-  }
-  pp_limit<R>(H, pA, mA, pB, mB, mu);
+  pp_limit<R>(H, [&](int c, int k) { return (k & 1) ? fm[c][3 + (k >> 1)] : fp[c][3 + (k >> 1)]; }, mu);
 }
 
 template <class R, int S, int AX, bool LAST>
@@ -329,15 +308,8 @@ constexpr int kTileXP = kTileX;      // x pitch of the LDS arrays (128-byte rows
 // between the points in slots f + 3 and f + 4, column col.
 template <class R, int kP, int kPitch>
 __device__ __forceinline__ void tile_limit(R H[5], const R* sFp, const R* sFm, int f, int col, double mu) {
-  R pA[5], mA[5], pB[5], mB[5];
-#pragma unroll
-  for (int c = 0; c < 5; ++c) {
-    pA[c] = sFp[(c * kP + f + 3) * kPitch + col];
-    mA[c] = sFm[(c * kP + f + 3) * kPitch + col];
-    pB[c] = sFp[(c * kP + f + 4) * kPitch + col];
-    mB[c] = sFm[(c * kP + f + 4) * kPitch + col];
-  }
-  pp_limit<R>(H, pA, mA, pB, mB, mu);
+  pp_limit<R>(
+      H, [&](int c, int k) { return ((k & 1) ? sFm : sFp)[(c * kP + f + 3 + (k >> 1)) * kPitch + col]; }, mu);
 }
 
 template <class R, int S, int AX, bool LAST, int kTileA>
