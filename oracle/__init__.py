@@ -22,6 +22,10 @@ Parity status per function (pins in tests/test_oracle_*.py):
   eps2             pinned (closed form on a separable field)
   eps2_complex_step pinned (central finite differences of run)
   jvp              pinned (central finite differences of run)
+  musta_flux, run with flux="musta"
+                   pinned (consistency, stage fixed point, mirror symmetry,
+                   second order on smooth data, Riemann convergence with
+                   near-monotone profiles, conservation, symmetries)
   limit_face, run with limiter="pp"
                    pinned (admissibility invariant, brute-force largest
                    theta, exact root for linear constraints, inactive on
@@ -55,6 +59,8 @@ class OCfg(ctypes.Structure):
         ("eos_dof", ctypes.c_double),
         ("hbarc", ctypes.c_double),
         ("limiter", ctypes.c_int32),
+        ("flux", ctypes.c_int32),
+        ("musta_k", ctypes.c_int32),
     ]
 
 
@@ -74,6 +80,7 @@ WENO = {"z": 0, "js": 1, "linear": 2, "z5": 3, "js5": 4, "linear5": 5}
 BC = {"outflow": 0, "periodic": 1}
 DEPOSIT = {"ngp": 0, "gauss": 1}
 LIMITER = {"none": 0, "pp": 1}
+FLUX = {"weno": 0, "musta": 1}
 
 
 def _load():
@@ -108,8 +115,10 @@ def _load():
                                              ctypes.c_int, ctypes.c_double, dp, dp, dp]
     lib.oracle_jvp.argtypes = [cp, jp, ctypes.c_int, dp, dp, ctypes.c_int, ctypes.c_double, dp, dp]
     lib.oracle_limit_face.argtypes = [cp, ctypes.c_int, dp, dp, dp, dp]
+    lib.oracle_musta_flux.argtypes = [ctypes.c_int, dp, dp, ctypes.c_int, dp, dp, dp]
     for name in ("oracle_prim_to_cons", "oracle_cons_to_prim", "oracle_rhs", "oracle_run",
-                 "oracle_sums", "oracle_eps2", "oracle_eps2_complex_step", "oracle_jvp", "oracle_limit_face"):
+                 "oracle_sums", "oracle_eps2", "oracle_eps2_complex_step", "oracle_jvp", "oracle_limit_face",
+                 "oracle_musta_flux"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -135,6 +144,8 @@ class Problem:
     eos_dof: float = 47.5
     hbarc: float = 0.1973269804
     limiter: str = "none"
+    flux: str = "weno"      # "weno": WENO of the LF split fluxes; "musta": MUSTA-FORCE
+    musta_k: int = 2
 
     def c(self) -> OCfg:
         c = OCfg()
@@ -150,6 +161,8 @@ class Problem:
         c.eos_dof = float(self.eos_dof)
         c.hbarc = float(self.hbarc)
         c.limiter = LIMITER[self.limiter] if isinstance(self.limiter, str) else int(self.limiter)
+        c.flux = FLUX[self.flux] if isinstance(self.flux, str) else int(self.flux)
+        c.musta_k = int(self.musta_k)
         return c
 
     @property
@@ -338,3 +351,13 @@ def limit_face(pb: Problem, d: int, uA, uB, H):
     rc = _load().oracle_limit_face(ctypes.byref(c), int(d), _dp(uA), _dp(uB), _dp(Hc), ctypes.byref(th))
     assert rc == 0
     return Hc, th.value
+
+
+def musta_flux(d: int, uL, uR, k: int, states: bool = False):
+    """MUSTA-FORCE flux along axis d of the face states uL, uR (k stages); with
+    states=True also the local states the last stage started from."""
+    a = np.ascontiguousarray(uL, dtype=np.float64)
+    b = np.ascontiguousarray(uR, dtype=np.float64)
+    F, ak, bk = np.empty(5), np.empty(5), np.empty(5)
+    assert _load().oracle_musta_flux(int(d), _dp(a), _dp(b), int(k), _dp(F), _dp(ak), _dp(bk)) == 0
+    return (F, ak, bk) if states else F

@@ -75,6 +75,8 @@ typedef struct {
   double eos_dof;     // g in e = g pi^2/30 T^4 / (hbar c)^3   (47.5)
   double hbarc;       // hbar c [GeV fm]                           (0.1973269804)
   int32_t limiter;    // 0 = none, 1 = positivity-preserving flux limiter
+  int32_t flux;       // 0 = WENO of the Lax-Friedrichs split fluxes, 1 = MUSTA-FORCE
+  int32_t musta_k;    // MUSTA stages (flux = 1), >= 1
 } ocfg;
 
 typedef struct {
@@ -393,6 +395,7 @@ struct Solver {
     for (int b = 0; b < n2; ++b) {
       for (int a = 0; a < n1; ++a) {
         std::vector<S> Fp(n + 8), Fm(n + 8), Fh(5 * (n + 1));
+        long long line_fx = 0;
         auto padded = [&](int P) {
           int idx[3];
           idx[d] = P;
@@ -400,7 +403,10 @@ struct Solver {
           idx[e2] = b + 4;
           return g.atp(idx[0], idx[1], idx[2]);
         };
-        for (int comp = 0; comp < 5; ++comp) {
+        if (c.flux == 1) {
+          musta_faces(d, padded, n, Fh.data(), &line_fx);
+        }
+        for (int comp = 0; comp < 5 && c.flux == 0; ++comp) {
           // split fluxes along the line, padded index P in [0, n+8)
           for (int P = 0; P < n + 8; ++P) {
             size_t q = padded(P);
@@ -447,6 +453,10 @@ struct Solver {
             for (int comp = 0; comp < 5; ++comp) Fh[comp * (n + 1) + i + 1] = H[comp];
           }
         }
+        if (line_fx) {
+#pragma omp atomic
+          fixups += line_fx;
+        }
         for (int comp = 0; comp < 5; ++comp) {
           const S* Fc = &Fh[comp * (n + 1)];
           for (int i = 0; i < n; ++i) {
@@ -459,6 +469,80 @@ struct Solver {
           }
         }
       }
+    }
+  }
+
+  // Physical flux along d of an arbitrary conserved state (recovered with the
+  // same fix-ups as the grid cells; fixed-up recoveries are counted in *fx).
+  static void state_flux(int d, const S u[5], S f[5], long long* fx) {
+    Prim<S> p = cons_to_prim(u[0], u[1], u[2], u[3], u[4], fx);
+    S pr = p.e / 3.0;
+    f[0] = u[1 + d];
+    for (int m = 0; m < 3; ++m) f[1 + m] = u[1 + m] * p.v[d] + (m == d ? pr : S(0.0));
+    f[4] = u[4] * p.v[d];
+  }
+
+  // MUSTA-FORCE flux (Toro's multi-stage centred flux) of the states uL, uR
+  // at one face, on a local two-cell mesh with dt_loc/dx_loc = C/S_max,
+  // C = 0.9, S_max = 1 (the speed of light).  Each stage forms the FORCE
+  // flux, the mean of the Lax-Friedrichs flux
+  //   (f(uL) + f(uR))/2 - (uR - uL)/(2 lam)
+  // and the flux of the Richtmyer state (uL + uR)/2 - lam (f(uR) - f(uL))/2;
+  // the last stage's FORCE flux is the result, the stages before it advance
+  // the local states: uL -= lam (F - f(uL)), uR -= lam (f(uR) - F).
+  static constexpr double kMustaCfl = 0.9;
+
+  static void musta_force(int d, S uL[5], S uR[5], int k, S F[5], long long* fx) {
+    const double lam = kMustaCfl;
+    for (int l = 1; l <= k; ++l) {
+      S fL[5], fR[5], uM[5], fM[5];
+      state_flux(d, uL, fL, fx);
+      state_flux(d, uR, fR, fx);
+      for (int m = 0; m < 5; ++m) uM[m] = 0.5 * (uL[m] + uR[m]) - 0.5 * lam * (fR[m] - fL[m]);
+      state_flux(d, uM, fM, fx);
+      for (int m = 0; m < 5; ++m) {
+        S flf = 0.5 * (fL[m] + fR[m]) - (0.5 / lam) * (uR[m] - uL[m]);
+        F[m] = 0.5 * (flf + fM[m]);
+      }
+      if (l == k) return;
+      for (int m = 0; m < 5; ++m) {
+        uL[m] = uL[m] - lam * (F[m] - fL[m]);
+        uR[m] = uR[m] - lam * (fR[m] - F[m]);
+      }
+    }
+  }
+
+  // Faces of one line with the MUSTA-FORCE flux of the left and right states
+  // reconstructed component-wise from the conserved point values by the
+  // configured WENO scheme (the left state from cells i-3..i+3, the right
+  // one from the mirrored stencil i+4..i-2; WENO5: i-2..i+2 and i+3..i-1).
+  template <class Padded>
+  void musta_faces(int d, Padded padded, int n, S* Fh, long long* fx) const {
+    const size_t np = g.npad();
+    for (int i = -1; i < n; ++i) {
+      int P = i + 4;
+      S uL[5], uR[5], F[5];
+      for (int comp = 0; comp < 5; ++comp) {
+        if (c.weno >= 3) {
+          S left[5], right[5];
+          for (int m = 0; m < 5; ++m) {
+            left[m] = Wp[comp * np + padded(P - 2 + m)];
+            right[m] = Wp[comp * np + padded(P + 3 - m)];
+          }
+          uL[comp] = weno5_left(left, c.weno - 3, c.weno_eps, c.weno_p);
+          uR[comp] = weno5_left(right, c.weno - 3, c.weno_eps, c.weno_p);
+        } else {
+          S left[7], right[7];
+          for (int m = 0; m < 7; ++m) {
+            left[m] = Wp[comp * np + padded(P - 3 + m)];
+            right[m] = Wp[comp * np + padded(P + 4 - m)];
+          }
+          uL[comp] = weno7_left(left, c.weno, c.weno_eps, c.weno_p);
+          uR[comp] = weno7_left(right, c.weno, c.weno_eps, c.weno_p);
+        }
+      }
+      musta_force(d, uL, uR, c.musta_k, F, fx);
+      for (int comp = 0; comp < 5; ++comp) Fh[comp * (n + 1) + i + 1] = F[comp];
     }
   }
 
@@ -719,6 +803,7 @@ bool valid(const ocfg* c) {
   }
   if (c->weno < 0 || c->weno > 5 || c->deposit < 0 || c->deposit > 1 || c->weno_p < 1) return false;
   if (c->limiter < 0 || c->limiter > 1) return false;
+  if (c->flux < 0 || c->flux > 1 || (c->flux == 1 && (c->musta_k < 1 || c->limiter != 0))) return false;
   return c->dt > 0.0;
 }
 
@@ -906,6 +991,24 @@ int oracle_limit_face(const ocfg* c, int d, const double* uA, const double* uB, 
   }
   const double mu = 2.0 * c->dt * (1.0 / c->dx[0] + 1.0 / c->dx[1] + 1.0 / c->dx[2]);
   *theta = Solver<double>::limit_face_mu(mu, uA, fA, uB, fB, H);
+  return 0;
+}
+
+// MUSTA-FORCE flux along axis d of the face states uL, uR with k stages;
+// uLk, uRk (may be NULL) receive the local states the last stage started from.
+int oracle_musta_flux(int d, const double* uL, const double* uR, int k, double* F, double* uLk, double* uRk) {
+  if (d < 0 || d > 2 || k < 1) return -1;
+  double a[5], b[5];
+  for (int m = 0; m < 5; ++m) {
+    a[m] = uL[m];
+    b[m] = uR[m];
+  }
+  long long fx = 0;
+  Solver<double>::musta_force(d, a, b, k, F, &fx);
+  for (int m = 0; m < 5; ++m) {
+    if (uLk) uLk[m] = a[m];
+    if (uRk) uRk[m] = b[m];
+  }
   return 0;
 }
 
