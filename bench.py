@@ -50,8 +50,17 @@ SCHEME_NAMES = {"z": "WENO7-Z", "js": "WENO7-JS", "linear": "WENO7 linear weight
                 "js5": "WENO5-JS", "linear5": "WENO5 linear weights"}
 
 
-def flops_per_cell(weno: str = "z"):
+# MUSTA-FORCE per face and stage: three recoveries with their fluxes (3 x 31),
+# the Richtmyer state (20) and the FORCE flux (30); the local update between
+# stages (30).
+MUSTA_STAGE_FLOPS, MUSTA_UPDATE_FLOPS = 3 * 31 + 20 + 30, 30
+
+
+def flops_per_cell(weno: str = "z", flux: str = "weno", musta_k: int = 2):
     r = 10 * RECON_FLOPS[weno]
+    if flux == "musta":  # reconstructions of the two states, stages, divergence (+ combine in z)
+        f = r + MUSTA_STAGE_FLOPS * musta_k + MUSTA_UPDATE_FLOPS * (musta_k - 1) + 10
+        return {"xface": f, "ymarch": f, "zmarch": f + 15}
     return {"xface": r + 25 + 10 + 25, "ymarch": r + 25 + 10, "zmarch": r + 25 + 10 + 15}
 
 
@@ -227,6 +236,9 @@ def main():
     ap.add_argument("--x", choices=["row", "tile"], default="row", help="x face kernel")
     ap.add_argument("--limiter", choices=["none", "pp"], default="none",
                     help="face-flux limiter of the stage run (pp: positivity-preserving)")
+    ap.add_argument("--flux", choices=["weno", "musta"], default="weno",
+                    help="face fluxes of the stage run: WENO of the LF split fluxes, or MUSTA-FORCE")
+    ap.add_argument("--musta-k", type=int, default=2, help="MUSTA-FORCE stages")
     ap.add_argument("--weno", choices=sorted(RECON_FLOPS), default="z",
                     help="reconstruction: WENO7 (z, js, linear) or WENO5 (z5, js5, linear5)")
     ap.add_argument("--adjoint-n", type=int, default=128, help="grid edge of the differentiable run (0: skip)")
@@ -262,8 +274,9 @@ def main():
         return
 
     w = W.paper_event(2, n=(args.n,) * 3)
-    h = H.from_workload(w, precision=args.precision, weno=args.weno, limiter=args.limiter)
-    fpc = flops_per_cell(args.weno)  # the limiter's own arithmetic is not counted
+    h = H.from_workload(w, precision=args.precision, weno=args.weno, limiter=args.limiter, flux=args.flux,
+                        musta_k=args.musta_k)
+    fpc = flops_per_cell(args.weno, args.flux, args.musta_k)  # the limiter's own arithmetic is not counted
     fpc_update = sum(fpc.values())
     h.set_option(H.OPT_YZ_KERNEL, 0 if args.yz == "tile" else 1)
     h.set_option(H.OPT_X_KERNEL, 0 if args.x == "row" else 1)
@@ -297,7 +310,7 @@ def main():
     peak = PEAK_TFLOPS[args.precision]
     traffic = None
     rec = (MEASURED_TRAFFIC.get((dom, args.precision, args.yz, args.n))
-           if args.weno == "z" and args.limiter == "none" else None)
+           if args.weno == "z" and args.limiter == "none" and args.flux == "weno" else None)
     if rec is not None:
         import hashlib
         src = os.path.join(ROOT, "paper_1511_02137_amd", "csrc", "hydro_kernels.hip")
@@ -325,11 +338,14 @@ def main():
         "dtype": args.precision,
         "data": "synthetic",
         "config": {"workload": "%s: %d^3 cells, dx 0.1 fm, dt 0.02 fm/c, p = e/3, %s + LF split%s, "
-                               "SSP-RK3, 1 jet (NGP), outflow" % (w.name, args.n, SCHEME_NAMES[args.weno],
-                                                                  " + positivity limiter" if args.limiter == "pp"
-                                                                  else ""),
+                               "SSP-RK3, 1 jet (NGP), outflow" % (
+                                   w.name, args.n, SCHEME_NAMES[args.weno],
+                                   (" + positivity limiter" if args.limiter == "pp" else "") +
+                                   (" (MUSTA-FORCE fluxes, %d stages, of the WENO states)" % args.musta_k
+                                    if args.flux == "musta" else "")),
                    "grid": list(w.n), "precision": args.precision, "jets": len(w.jets), "yz_kernel": args.yz,
-                   "x_kernel": args.x, "weno": args.weno, "limiter": args.limiter},
+                   "x_kernel": args.x, "weno": args.weno, "limiter": args.limiter, "flux": args.flux,
+                   "musta_k": args.musta_k if args.flux == "musta" else None},
         "roofline": roofline,
         "step_alu_frac": step_frac,
         "flops_per_cell_update": fpc_update,

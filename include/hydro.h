@@ -92,6 +92,17 @@ typedef enum {
  * hydro_adjoint_step does not support it (HYDRO_EINVAL). */
 typedef enum { HYDRO_LIMITER_NONE = 0, HYDRO_LIMITER_PP = 1 } hydro_limiter;
 
+/* Face flux.  HYDRO_FLUX_WENO_LF (default): WENO reconstruction of the
+ * Lax-Friedrichs split fluxes (section "Simulation setup").
+ * HYDRO_FLUX_MUSTA: the MUSTA-FORCE flux the paper names as its other solver
+ * (Toro's multi-stage FORCE flux): the face states are the WENO
+ * reconstructions (cfg.weno, WENO7-Z or WENO5-Z) of the conserved values from
+ * the left (cells i-3..i+3) and from the right (the mirrored stencil), and
+ * cfg.musta_k stages of the FORCE flux on a local two-cell mesh with
+ * dt/dx = 0.9 (wave speeds bounded by 1) give the face flux.  Second order on
+ * point values.  Not with the limiter; hydro_adjoint_step refuses it. */
+typedef enum { HYDRO_FLUX_WENO_LF = 0, HYDRO_FLUX_MUSTA = 1 } hydro_flux;
+
 typedef struct {
   int32_t n[3];        /* cells along x, y, z >= 1; n[0] <= 810 (FP64) or 1024 (FP32),
                           n[1], n[2] <= 65535 */
@@ -108,6 +119,8 @@ typedef struct {
   double eos_dof;      /* g of e = g pi^2/30 T^4/(hbar c)^3; 47.5 */
   double hbarc;        /* hbar c [GeV fm]; 0.1973269804 */
   int32_t limiter;     /* hydro_limiter (default HYDRO_LIMITER_NONE) */
+  int32_t flux;        /* hydro_flux (default HYDRO_FLUX_WENO_LF) */
+  int32_t musta_k;     /* MUSTA-FORCE stages, 1..8 (default 2) */
 } hydro_config;
 
 /* One jet (Eq. 2, 3): a straight line at the speed of light from x0 in
@@ -130,7 +143,7 @@ typedef struct hydro_ctx hydro_ctx;
 
 /* Fill *cfg with the defaults: the paper's 256^3 shape, dx = 0.1 fm,
  * dt = 0.02 fm/c, t0 = 1 fm/c, outflow, FP64, WENO-Z, NGP deposit, no
- * limiter. */
+ * limiter, WENO-LF face fluxes (musta_k = 2). */
 void hydro_default_config(hydro_config* cfg);
 
 /* Bytes of caller-provided device workspace that hydro_init needs for cfg:

@@ -161,6 +161,7 @@ hipError_t stage_impl(hydro_ctx* ctx, const R* W, const R* Un, R* out, int stage
   a.out = out;
   a.D = static_cast<R*>(ctx->D);
   a.pp_mu = pp_mu(c);
+  a.musta_k = c.musta_k;
   const int scheme = face_scheme(c);
   hipError_t e;
   {
@@ -230,8 +231,8 @@ bool adjoint_fits(const hydro_config* c, std::string* why) {
     if (why) *why = "the adjoint is built for the WENO7 schemes only";
     return false;
   }
-  if (c->limiter != HYDRO_LIMITER_NONE) {
-    if (why) *why = "the adjoint is built without the flux limiter";
+  if (c->limiter != HYDRO_LIMITER_NONE || c->flux != HYDRO_FLUX_WENO_LF) {
+    if (why) *why = "the adjoint is built for WENO-LF fluxes without the limiter";
     return false;
   }
   for (int d = 0; d < 3; ++d) {
@@ -357,6 +358,8 @@ void hydro_default_config(hydro_config* c) {
   c->eos_dof = 47.5;
   c->hbarc = 0.1973269804;
   c->limiter = HYDRO_LIMITER_NONE;
+  c->flux = HYDRO_FLUX_WENO_LF;
+  c->musta_k = 2;
 }
 
 size_t hydro_workspace_bytes(const hydro_config* cfg, int adjoint_k) {

@@ -76,7 +76,7 @@ void drop_graph(hydro_batch* b) {
 
 bool compatible(const hydro_config& a, const hydro_config& c) {
   return a.precision == c.precision && a.weno == c.weno && a.weno_eps == c.weno_eps && a.weno_p == c.weno_p &&
-         a.limiter == c.limiter;
+         a.limiter == c.limiter && a.flux == c.flux && a.musta_k == c.musta_k;
 }
 
 size_t field_bytes(const hydro_config& c) { return align256((size_t)5 * ncells(&c) * elem_size(&c)); }
@@ -162,7 +162,8 @@ std::string tune_key(const hydro_batch* b) {
   int dev = 0;
   (void)hipGetDevice(&dev);
   if (hipGetDeviceProperties(&p, dev) == hipSuccess) k << p.gcnArchName << ":" << p.multiProcessorCount;
-  k << ":p" << b->cfg[0].precision << ":w" << b->cfg[0].weno << ":l" << b->cfg[0].limiter;
+  k << ":p" << b->cfg[0].precision << ":w" << b->cfg[0].weno << ":l" << b->cfg[0].limiter << ":f" << b->cfg[0].flux
+    << ":" << b->cfg[0].musta_k;
   for (const auto& s : shapes) k << ":" << s;
   unsigned long long h = 1469598103934665603ULL;
   for (unsigned char ch : k.str()) {
@@ -374,6 +375,7 @@ int hydro_batch_create(const hydro_config* cfgs, int n_events, const double* con
     for (int d = 0; d < 3; ++d) v.inv_d[d] = 1.0 / c.dx[d];
     v.dV = c.dx[0] * c.dx[1] * c.dx[2];
     v.pp_mu = pp_mu(c);
+    v.musta_k = c.musta_k;
     v.eos_dof = c.eos_dof;
     v.hbarc = c.hbarc;
     v.njet = 0;

@@ -254,6 +254,64 @@ __device__ __forceinline__ R face_flux(const R* fp, const R* fm, R eps) {
 }
 
 // ---------------------------------------------------------------------------
+// MUSTA-FORCE flux (Toro's multi-stage centred flux), the alternative solver:
+// kernels take it as the flag kMusta on the scheme template argument and then
+// keep the conserved values (not the split fluxes) in their LDS tiles.  The
+// face states uL, uR come from the WENO reconstruction of those values; on a
+// local two-cell mesh with dt/dx = 0.9 (S_max = 1) each stage forms the FORCE
+// flux, the mean of the Lax-Friedrichs flux (fL + fR)/2 - (uR - uL)/(2 * 0.9)
+// and the flux of the Richtmyer state (uL + uR)/2 - 0.45 (fR - fL); the last
+// stage's FORCE flux is the face flux, the stages before it move the local
+// states: uL -= 0.9 (F - fL), uR -= 0.9 (fR - F).  Recovery in FP64 as
+// everywhere; fixed-up recoveries are counted.
+template <class R, int AX>
+__device__ __forceinline__ void phys_flux(const R u[5], R f[5], unsigned& fix) {
+  const PrimV p = c2p(u, fix);
+  const R vd = (R)p.v[AX];
+  const R pr = (R)(p.e * (1.0 / 3.0));
+  f[0] = u[1 + AX];
+  f[1] = (AX == 0) ? u[1] * vd + pr : u[1] * vd;
+  f[2] = (AX == 1) ? u[2] * vd + pr : u[2] * vd;
+  f[3] = (AX == 2) ? u[3] * vd + pr : u[3] * vd;
+  f[4] = u[4] * vd;
+}
+
+template <class R, int AX>
+__device__ __forceinline__ void musta_force(R uL[5], R uR[5], int k, R F[5], unsigned& fix) {
+  for (int l = 1;; ++l) {
+    R fL[5], fR[5], uM[5], fM[5];
+    phys_flux<R, AX>(uL, fL, fix);
+    phys_flux<R, AX>(uR, fR, fix);
+#pragma unroll
+    for (int c = 0; c < 5; ++c) uM[c] = R(0.5) * (uL[c] + uR[c]) - R(0.45) * (fR[c] - fL[c]);
+    phys_flux<R, AX>(uM, fM, fix);
+#pragma unroll
+    for (int c = 0; c < 5; ++c) F[c] = R(0.5) * ((R(0.5) * (fL[c] + fR[c]) - R(0.5 / 0.9) * (uR[c] - uL[c])) + fM[c]);
+    if (l >= k) return;
+#pragma unroll
+    for (int c = 0; c < 5; ++c) {
+      uL[c] = uL[c] - R(0.9) * (F[c] - fL[c]);
+      uR[c] = uR[c] - R(0.9) * (fR[c] - F[c]);
+    }
+  }
+}
+
+// One face with the MUSTA-FORCE flux: at(c, m) is component c of the
+// conserved value at window point m = 0..7 (points i-3..i+4 for face i+1/2);
+// uL from points 0..6, uR from the mirrored stencil 7..1 (WENO5: the middle
+// five of each).
+template <class R, int SC, int AX, class At>
+__device__ __forceinline__ void musta_face(At at, R eps, int k, R F[5], unsigned& fix) {
+  R uL[5], uR[5];
+#pragma unroll
+  for (int c = 0; c < 5; ++c) {
+    uL[c] = weno7<R, SC>(at(c, 0), at(c, 1), at(c, 2), at(c, 3), at(c, 4), at(c, 5), at(c, 6), eps);
+    uR[c] = weno7<R, SC>(at(c, 7), at(c, 6), at(c, 5), at(c, 4), at(c, 3), at(c, 2), at(c, 1), eps);
+  }
+  musta_force<R, AX>(uL, uR, k, F, fix);
+}
+
+// ---------------------------------------------------------------------------
 // Positivity-preserving flux limiter (after Zhang and Shu).  Kernels take it
 // as the flag kPP on the scheme template argument.
 //

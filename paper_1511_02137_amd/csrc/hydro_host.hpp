@@ -39,6 +39,12 @@ inline bool config_ok(const hydro_config* c, std::string* why) {
   if (c->precision != HYDRO_F64 && c->precision != HYDRO_F32) return fail("bad precision");
   if (c->weno < 0 || c->weno > 5) return fail("bad weno");
   if (c->limiter != HYDRO_LIMITER_NONE && c->limiter != HYDRO_LIMITER_PP) return fail("bad limiter");
+  if (c->flux != HYDRO_FLUX_WENO_LF && c->flux != HYDRO_FLUX_MUSTA) return fail("bad flux");
+  if (c->flux == HYDRO_FLUX_MUSTA) {
+    if (c->musta_k < 1 || c->musta_k > 8) return fail("musta_k must be in [1, 8]");
+    if (c->weno != HYDRO_WENO_Z && c->weno != HYDRO_WENO5_Z) return fail("MUSTA-FORCE is built with WENO7-Z or WENO5-Z states");
+    if (c->limiter != HYDRO_LIMITER_NONE) return fail("MUSTA-FORCE is built without the limiter");
+  }
   if (c->deposit != HYDRO_DEP_NGP && c->deposit != HYDRO_DEP_GAUSS) return fail("bad deposit");
   if (!(c->weno_eps > 0.0)) return fail("weno_eps must be > 0");
   if (c->weno_p != 2) return fail("only weno_p = 2 is built");
@@ -47,8 +53,10 @@ inline bool config_ok(const hydro_config* c, std::string* why) {
 }
 
 // Template scheme argument of the face kernels: the WENO scheme, plus kPP
-// with the positivity-preserving limiter.
-inline int face_scheme(const hydro_config& c) { return c.weno | (c.limiter == HYDRO_LIMITER_PP ? kPP : 0); }
+// with the positivity-preserving limiter, plus kMusta with MUSTA-FORCE fluxes.
+inline int face_scheme(const hydro_config& c) {
+  return c.weno | (c.limiter == HYDRO_LIMITER_PP ? kPP : 0) | (c.flux == HYDRO_FLUX_MUSTA ? kMusta : 0);
+}
 
 // Half-state factor of the positivity-preserving limiter: 2 dt sum_d 1/dx_d.
 inline double pp_mu(const hydro_config& c) { return 2.0 * c.dt * ((1.0 / c.dx[0] + 1.0 / c.dx[1]) + 1.0 / c.dx[2]); }

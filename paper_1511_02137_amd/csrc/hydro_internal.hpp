@@ -18,6 +18,9 @@ enum Scheme { kWenoZ = 0, kWenoJS = 1, kWenoLinear = 2, kWeno5Z = 3, kWeno5JS = 
 // Flag on the face kernels' scheme template argument: positivity-preserving
 // flux limiter on.
 constexpr int kPP = 8;
+// Flag on the same argument: MUSTA-FORCE face fluxes of WENO-reconstructed
+// conserved states instead of WENO of the Lax-Friedrichs split fluxes.
+constexpr int kMusta = 16;
 
 // Grid of one event.
 struct Grid {
@@ -60,6 +63,7 @@ struct StageArgs {
   int seg;      // march segment length (y/z kernels)
   unsigned long long* fixups;
   double pp_mu;  // 2 dt sum_d 1/dx_d, the half-state factor of the positivity limiter
+  int musta_k;   // MUSTA-FORCE stages
 };
 
 // Arguments of the jet kernel.
@@ -134,6 +138,7 @@ struct BatchEvent {
   double dV;
   double eos_dof, hbarc;
   double pp_mu;       // 2 dt sum_d 1/dx_d (positivity limiter)
+  int musta_k;        // MUSTA-FORCE stages
   int njet;
   int deposit;
 };

@@ -38,6 +38,23 @@ namespace hydro {
 // (also into every ghost slot that copies the cell), reconstructs the cell's
 // left face and forms the divergence; the outflow right face of the last cell
 // is added by k_xbound.
+// What the face kernels keep per point: the Lax-Friedrichs split fluxes
+// (F+, F-), or with MUSTA-FORCE the conserved values themselves (in the F+
+// slots; no recovery needed).
+template <class R, int S, int AX>
+__device__ __forceinline__ void point_values(const R u[5], R Fp[5], R Fm[5], unsigned& fix) {
+  if constexpr ((S & kMusta) != 0) {
+#pragma unroll
+    for (int c = 0; c < 5; ++c) {
+      Fp[c] = u[c];
+      Fm[c] = R(0);
+    }
+  } else {
+    const PrimV pv = c2p(u, fix);
+    split_flux<R, AX>(u, pv, Fp, Fm);
+  }
+}
+
 template <class R, int S>
 __device__ __forceinline__ void xrows_body(const StageArgs<R>& a, long long row0, int rpi, R* s) {
   const int nx = a.g.n[0];
@@ -56,9 +73,8 @@ __device__ __forceinline__ void xrows_body(const StageArgs<R>& a, long long row0
   if (act) {
     R u[5];
     load5(a.W, nc, rowbase + x, u);
-    const PrimV pv = c2p(u, fix);
     R Fp[5], Fm[5];
-    split_flux<R, 0>(u, pv, Fp, Fm);
+    point_values<R, S, 0>(u, Fp, Fm, fix);
 #pragma unroll
     for (int c = 0; c < 5; ++c) {
       sFp[c * P + x + 4] = Fp[c];
@@ -81,7 +97,10 @@ __device__ __forceinline__ void xrows_body(const StageArgs<R>& a, long long row0
   if (act) {
     // face x - 1/2: F+ at x-4..x+2 (slots x..x+6), F- at x-3..x+3 (slots x+1..x+7)
 #pragma unroll
-    for (int c = 0; c < 5; ++c) Fh[c] = face_flux<R, (S & 7)>(sFp + c * P + x, sFm + c * P + x, a.eps);
+    for (int c = 0; c < 5 && (S & kMusta) == 0; ++c)
+      Fh[c] = face_flux<R, (S & 7)>(sFp + c * P + x, sFm + c * P + x, a.eps);
+    if constexpr ((S & kMusta) != 0)
+      musta_face<R, (S & 7), 0>([&](int c, int m) { return sFp[c * P + x + m]; }, a.eps, a.musta_k, Fh, fix);
     if constexpr ((S & kPP) != 0) {  // cells x - 1 and x: slots x + 3 and x + 4
       pp_limit<R>(
           Fh, [&](int c, int k) { return ((k & 1) ? sFm : sFp)[c * P + x + 3 + (k >> 1)]; }, a.pp_mu);
@@ -139,9 +158,8 @@ __device__ __forceinline__ void xbound_body(const StageArgs<R>& a, long long gro
     if (row < rows) {
       R u[5];
       load5(a.W, nc, row * nx + map_idx(nx - 4 + m, nx, 0), u);
-      const PrimV pv = c2p(u, fix);
       R Fp[5], Fm[5];
-      split_flux<R, 0>(u, pv, Fp, Fm);
+      point_values<R, S, 0>(u, Fp, Fm, fix);
 #pragma unroll
       for (int c = 0; c < 5; ++c) {
         sF[l][m][c] = Fp[c];
@@ -154,14 +172,30 @@ __device__ __forceinline__ void xbound_body(const StageArgs<R>& a, long long gro
     const int l = t / 10, r = t % 10, c = r >> 1;
     const long long row = group * kXBoundRows + l;
     if (row < rows) {
+      const int cm = ((S & kMusta) != 0) ? c : 5 + c;  // MUSTA: both states from the conserved values
       sR[l][r] = (r & 1) == 0
                      ? weno7<R, (S & 7)>(sF[l][0][c], sF[l][1][c], sF[l][2][c], sF[l][3][c], sF[l][4][c], sF[l][5][c],
                                    sF[l][6][c], a.eps)
-                     : weno7<R, (S & 7)>(sF[l][7][5 + c], sF[l][6][5 + c], sF[l][5][5 + c], sF[l][4][5 + c],
-                                   sF[l][3][5 + c], sF[l][2][5 + c], sF[l][1][5 + c], a.eps);
+                     : weno7<R, (S & 7)>(sF[l][7][cm], sF[l][6][cm], sF[l][5][cm], sF[l][4][cm],
+                                   sF[l][3][cm], sF[l][2][cm], sF[l][1][cm], a.eps);
     }
   }
   __syncthreads();
+  if constexpr ((S & kMusta) != 0) {  // one lane per row: the MUSTA-FORCE flux of (uL, uR)
+    if (t < kXBoundRows && group * kXBoundRows + t < rows) {
+      const int l = t;
+      R uL[5], uR[5], F[5];
+#pragma unroll
+      for (int c = 0; c < 5; ++c) {
+        uL[c] = sR[l][2 * c];
+        uR[c] = sR[l][2 * c + 1];
+      }
+      musta_force<R, 0>(uL, uR, a.musta_k, F, fix);
+#pragma unroll
+      for (int c = 0; c < 5; ++c) sF[l][0][c] = F[c];  // point 0 is no longer read
+    }
+    __syncthreads();
+  }
   if constexpr ((S & kPP) != 0) {  // one lane per row: cell nx-1 (point 3) and its copy (point 4)
     if (t < kXBoundRows && group * kXBoundRows + t < rows) {
       const int l = t;
@@ -178,7 +212,7 @@ __device__ __forceinline__ void xbound_body(const StageArgs<R>& a, long long gro
     const int l = t / 5, c = t % 5;
     const long long row = group * kXBoundRows + l;
     if (row < rows) {
-      const R r = ((S & kPP) != 0) ? sF[l][0][c] : sR[l][2 * c] + sR[l][2 * c + 1];
+      const R r = ((S & (kPP | kMusta)) != 0) ? sF[l][0][c] : sR[l][2 * c] + sR[l][2 * c + 1];
       R* d = a.D + c * nc + row * nx + nx - 1;
       *d = (*d - r) * a.inv_d;
     }
@@ -222,19 +256,25 @@ __global__ void __launch_bounds__(256) k_march(StageArgs<R> a) {
   for (int m = 0; m < 8; ++m) {
     R u[5];
     load5(a.W, nc, base + (long long)map_idx(i0 - 4 + m, n, bc) * stride, u);
-    const PrimV pv = c2p(u, fix);
     R Fp[5], Fm[5];
-    split_flux<R, AX>(u, pv, Fp, Fm);
+    point_values<R, S, AX>(u, Fp, Fm, fix);
 #pragma unroll
     for (int c = 0; c < 5; ++c) {
       fp[c][m] = Fp[c];
       fm[c][m] = Fm[c];
     }
   }
-  R prev[5];
+  auto face = [&](R fh[5]) {
+    if constexpr ((S & kMusta) != 0) {
+      musta_face<R, (S & 7), AX>([&](int c, int m) { return fp[c][m]; }, a.eps, a.musta_k, fh, fix);
+    } else {
 #pragma unroll
-  for (int c = 0; c < 5; ++c) prev[c] = face_flux<R, (S & 7)>(fp[c], fm[c], a.eps);
-  if constexpr ((S & kPP) != 0) march_limit<R>(prev, fp, fm, a.pp_mu);
+      for (int c = 0; c < 5; ++c) fh[c] = face_flux<R, (S & 7)>(fp[c], fm[c], a.eps);
+      if constexpr ((S & kPP) != 0) march_limit<R>(fh, fp, fm, a.pp_mu);
+    }
+  };
+  R prev[5];
+  face(prev);
 
   for (int i = i0; i < i1; ++i) {
 #pragma unroll
@@ -248,9 +288,8 @@ __global__ void __launch_bounds__(256) k_march(StageArgs<R> a) {
     {
       R u[5];
       load5(a.W, nc, base + (long long)map_idx(i + 4, n, bc) * stride, u);
-      const PrimV pv = c2p(u, fix);
       R Fp[5], Fm[5];
-      split_flux<R, AX>(u, pv, Fp, Fm);
+      point_values<R, S, AX>(u, Fp, Fm, fix);
 #pragma unroll
       for (int c = 0; c < 5; ++c) {
         fp[c][7] = Fp[c];
@@ -259,9 +298,7 @@ __global__ void __launch_bounds__(256) k_march(StageArgs<R> a) {
     }
     const long long cell = base + (long long)i * stride;
     R fh[5];
-#pragma unroll
-    for (int c = 0; c < 5; ++c) fh[c] = face_flux<R, (S & 7)>(fp[c], fm[c], a.eps);
-    if constexpr ((S & kPP) != 0) march_limit<R>(fh, fp, fm, a.pp_mu);
+    face(fh);
 #pragma unroll
     for (int c = 0; c < 5; ++c) {
       const R div = (prev[c] - fh[c]) * a.inv_d;
@@ -337,9 +374,8 @@ __device__ __forceinline__ void tile_body(const StageArgs<R>& a, int bx, int by,
     const int p = a0 + ta;
     if (xin && ta < kTileA) {
       load5(a.W, nc, base + (long long)map_idx(p, n, bc) * stride, own);
-      const PrimV pv = c2p(own, fix);
       R Fp[5], Fm[5];
-      split_flux<R, AX>(own, pv, Fp, Fm);
+      point_values<R, S, AX>(own, Fp, Fm, fix);
 #pragma unroll
       for (int c = 0; c < 5; ++c) {
         sFp[(c * kTileP + ta + 4) * kTileXP + tx] = Fp[c];
@@ -367,9 +403,8 @@ __device__ __forceinline__ void tile_body(const StageArgs<R>& a, int bx, int by,
     if (xin) {
       R u[5];
       load5(a.W, nc, base + (long long)map_idx(p, n, bc) * stride, u);
-      const PrimV pv = c2p(u, fix);
       R Fp[5], Fm[5];
-      split_flux<R, AX>(u, pv, Fp, Fm);
+      point_values<R, S, AX>(u, Fp, Fm, fix);
 #pragma unroll
       for (int c = 0; c < 5; ++c) {
         sFp[(c * kTileP + j) * kTileXP + tx] = Fp[c];
@@ -384,7 +419,13 @@ __device__ __forceinline__ void tile_body(const StageArgs<R>& a, int bx, int by,
   R Fh[5], Fh2[5];
   const bool has1 = xin && ta < nf;
   const bool has2 = (kTileA + 1) * kTileX > 512 && xin && threadIdx.x < kTileX && kTileA < nf;
-  if (has1) {
+  if constexpr ((S & kMusta) != 0) {  // face row f: points in slots f..f+7
+    auto at = [&](int f) {
+      return [=](int c, int m) { return sFp[(c * kTileP + f + m) * kTileXP + tx]; };
+    };
+    if (has1) musta_face<R, (S & 7), AX>(at(ta), a.eps, a.musta_k, Fh, fix);
+    if (has2) musta_face<R, (S & 7), AX>(at(kTileA), a.eps, a.musta_k, Fh2, fix);
+  } else if (has1) {
 #pragma unroll
     for (int c = 0; c < 5; ++c) {
       const R* fp = sFp + (c * kTileP + ta) * kTileXP + tx;
@@ -395,7 +436,7 @@ __device__ __forceinline__ void tile_body(const StageArgs<R>& a, int bx, int by,
                           fm[2 * kTileXP], fm[kTileXP], a.eps);
     }
   }
-  if (has2) {
+  if ((S & kMusta) == 0 && has2) {
 #pragma unroll
     for (int c = 0; c < 5; ++c) {
       const R* fp = sFp + (c * kTileP + kTileA) * kTileXP + tx;
@@ -485,9 +526,8 @@ __device__ __forceinline__ void xtile_body(const StageArgs<R>& a, int bx, int by
     if (y < ny) {
       R u[5];
       load5(a.W, nc, zbase + (long long)y * nx + map_idx(x0 - 4 + j, nx, bc), u);
-      const PrimV pv = c2p(u, fix);
       R Fp[5], Fm[5];
-      split_flux<R, 0>(u, pv, Fp, Fm);
+      point_values<R, S, 0>(u, Fp, Fm, fix);
 #pragma unroll
       for (int c = 0; c < 5; ++c) {
         sFp[(c * kXTileP + j) * kXTileY + r] = Fp[c];
@@ -505,7 +545,13 @@ __device__ __forceinline__ void xtile_body(const StageArgs<R>& a, int bx, int by
   const bool has1 = yin && f < nf;
   const bool has2 = (kXTileX + 1) * kXTileY > 512 && yin && threadIdx.x < kXTileY && kXTileX < nf;
   R Fh[5], Fh2[5];
-  if (has1) {
+  if constexpr ((S & kMusta) != 0) {  // face row f: points in slots f..f+7
+    auto at = [&](int fr) {
+      return [=](int c, int m) { return sFp[(c * kXTileP + fr + m) * kXTileY + r]; };
+    };
+    if (has1) musta_face<R, (S & 7), 0>(at(f), a.eps, a.musta_k, Fh, fix);
+    if (has2) musta_face<R, (S & 7), 0>(at(kXTileX), a.eps, a.musta_k, Fh2, fix);
+  } else if (has1) {
 #pragma unroll
     for (int c = 0; c < 5; ++c) {
       const R* fp = sFp + (c * kXTileP + f) * kXTileY + r;
@@ -516,7 +562,7 @@ __device__ __forceinline__ void xtile_body(const StageArgs<R>& a, int bx, int by
                           fm[2 * kXTileY], fm[kXTileY], a.eps);
     }
   }
-  if (has2) {
+  if ((S & kMusta) == 0 && has2) {
 #pragma unroll
     for (int c = 0; c < 5; ++c) {
       const R* fp = sFp + (c * kXTileP + kXTileX) * kXTileY + r;
@@ -798,6 +844,7 @@ __device__ __forceinline__ StageArgs<R> batch_stage_args(const BatchEvent& ev, i
   a.seg = 0;
   a.fixups = &ev.dev->fixups;
   a.pp_mu = ev.pp_mu;
+  a.musta_k = ev.musta_k;
   return a;
 }
 
@@ -992,6 +1039,8 @@ hipError_t launch_face_kernel(int kernel, const StageArgs<R>& a, int scheme, int
     case kWeno5Z | kPP: HYDRO_DISPATCH(kWeno5Z | kPP) break;
     case kWeno5JS | kPP: HYDRO_DISPATCH(kWeno5JS | kPP) break;
     case kWeno5Linear | kPP: HYDRO_DISPATCH(kWeno5Linear | kPP) break;
+    case kWenoZ | kMusta: HYDRO_DISPATCH(kWenoZ | kMusta) break;
+    case kWeno5Z | kMusta: HYDRO_DISPATCH(kWeno5Z | kMusta) break;
     default: HYDRO_DISPATCH(kWenoZ) break;
   }
 #undef HYDRO_DISPATCH
@@ -1080,6 +1129,8 @@ hipError_t launch_batch_axis(int AX, const BatchArgs<R>& b, int scheme, long lon
     case kWeno5Z | kPP: HYDRO_BAXIS(kWeno5Z | kPP) break;
     case kWeno5JS | kPP: HYDRO_BAXIS(kWeno5JS | kPP) break;
     case kWeno5Linear | kPP: HYDRO_BAXIS(kWeno5Linear | kPP) break;
+    case kWenoZ | kMusta: HYDRO_BAXIS(kWenoZ | kMusta) break;
+    case kWeno5Z | kMusta: HYDRO_BAXIS(kWeno5Z | kMusta) break;
     default: HYDRO_BAXIS(kWenoZ) break;
   }
 #undef HYDRO_BAXIS

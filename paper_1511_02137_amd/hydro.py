@@ -21,6 +21,7 @@ BC = {"outflow": 0, "periodic": 1}
 WENO = {"z": 0, "js": 1, "linear": 2, "z5": 3, "js5": 4, "linear5": 5}
 DEPOSIT = {"ngp": 0, "gauss": 1}
 LIMITER = {"none": 0, "pp": 1}
+FLUX = {"weno": 0, "musta": 1}
 
 EXPORTED = [
     "hydro_default_config", "hydro_workspace_bytes", "hydro_init", "hydro_add_jet", "hydro_rk3_step",
@@ -59,6 +60,8 @@ class Config(ctypes.Structure):
         ("eos_dof", ctypes.c_double),
         ("hbarc", ctypes.c_double),
         ("limiter", ctypes.c_int32),
+        ("flux", ctypes.c_int32),
+        ("musta_k", ctypes.c_int32),
     ]
 
 
@@ -144,7 +147,7 @@ def load_library(path: str = LIB_PATH):
 
 def make_config(n, dx=(0.1, 0.1, 0.1), dt=0.02, t0=1.0, bc=("outflow",) * 3, precision="f64", weno="z",
                 deposit="ngp", weno_eps=1e-6, strict=False, eos_dof=47.5, hbarc=0.1973269804,
-                limiter="none") -> Config:
+                limiter="none", flux="weno", musta_k=2) -> Config:
     lib = load_library()
     c = Config()
     lib.hydro_default_config(ctypes.byref(c))
@@ -160,6 +163,8 @@ def make_config(n, dx=(0.1, 0.1, 0.1), dt=0.02, t0=1.0, bc=("outflow",) * 3, pre
     c.strict = 1 if strict else 0
     c.eos_dof, c.hbarc = float(eos_dof), float(hbarc)
     c.limiter = LIMITER[limiter] if isinstance(limiter, str) else int(limiter)
+    c.flux = FLUX[flux] if isinstance(flux, str) else int(flux)
+    c.musta_k = int(musta_k)
     return c
 
 
@@ -360,9 +365,10 @@ class Hydro:
 
 
 def from_workload(w, precision: str = "f64", weno: str = "z", bc=None, adjoint_k: int = 0, device="cuda",
-                  limiter: str = "none") -> Hydro:
+                  limiter: str = "none", flux: str = "weno", musta_k: int = 2) -> Hydro:
     """Hydro for a paper_1511_02137_amd.workloads.Workload, with its jets."""
-    cfg = make_config(w.n, w.dx, w.dt, w.t0, bc or w.bc, precision, weno, w.deposit, limiter=limiter)
+    cfg = make_config(w.n, w.dx, w.dt, w.t0, bc or w.bc, precision, weno, w.deposit, limiter=limiter, flux=flux,
+                      musta_k=musta_k)
     h = Hydro(cfg, w.prim0, device=device, adjoint_k=adjoint_k)
     for j in w.jets:
         h.add_jet(j.x0, j.dir, j.E0, j.t_start, j.kappa_rad, j.kappa_coll, j.cr_over_cf)
@@ -481,9 +487,11 @@ class Batch:
             pass
 
 
-def batch_from_workloads(ws, precision: str = "f32", weno: str = "z", device="cuda", limiter: str = "none") -> Batch:
+def batch_from_workloads(ws, precision: str = "f32", weno: str = "z", device="cuda", limiter: str = "none",
+                         flux: str = "weno", musta_k: int = 2) -> Batch:
     """Batch of workloads.Workload events, with their jets."""
-    cfgs = [make_config(w.n, w.dx, w.dt, w.t0, w.bc, precision, weno, w.deposit, limiter=limiter) for w in ws]
+    cfgs = [make_config(w.n, w.dx, w.dt, w.t0, w.bc, precision, weno, w.deposit, limiter=limiter, flux=flux,
+                        musta_k=musta_k) for w in ws]
     b = Batch(cfgs, [w.prim0 for w in ws], device=device)
     for e, w in enumerate(ws):
         for j in w.jets:
