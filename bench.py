@@ -40,10 +40,13 @@ METRIC = "cell-updates/s per RK3 stage at 256^3 (% of roofline); adjoint/forward
 #   divergence 10 per axis; conserved->primitive 25 (counted once, x);
 #   RK combine 15 (z).
 # Flops per reconstruction for the other schemes, same accounting: WENO7-JS
-# drops tau (151); WENO5-Z: candidates 15, smoothness 45, tau 2, weights 15,
-# sum 2, combination 5, normalisation 1 = 85; WENO5-JS 83; linear weights:
-# candidates + combination (35 for WENO7, 20 for WENO5).
-RECON_FLOPS = {"z": 155, "js": 151, "linear": 35, "z5": 85, "js5": 83, "linear5": 20}
+# drops tau (151); linear weights: candidates + combination (35 for WENO7, 20
+# for WENO5).  For WENO5-Z/JS the plain formulation (counted operation by
+# operation by the oracle's counting scalar: 78 and 71) needs fewer than the
+# library's form (85, 83), so the smaller count is used: the algorithmic count
+# is never taken above what a plain implementation needs (the test of the
+# counts checks this for every scheme).
+RECON_FLOPS = {"z": 155, "js": 151, "linear": 35, "z5": 78, "js5": 71, "linear5": 20}
 
 
 SCHEME_NAMES = {"z": "WENO7-Z", "js": "WENO7-JS", "linear": "WENO7 linear weights", "z5": "WENO5-Z",

@@ -116,9 +116,10 @@ def _load():
     lib.oracle_jvp.argtypes = [cp, jp, ctypes.c_int, dp, dp, ctypes.c_int, ctypes.c_double, dp, dp]
     lib.oracle_limit_face.argtypes = [cp, ctypes.c_int, dp, dp, dp, dp]
     lib.oracle_musta_flux.argtypes = [ctypes.c_int, dp, dp, ctypes.c_int, dp, dp, dp]
+    lib.oracle_count_flops.argtypes = [ctypes.c_int, ctypes.c_int, llp]
     for name in ("oracle_prim_to_cons", "oracle_cons_to_prim", "oracle_rhs", "oracle_run",
                  "oracle_sums", "oracle_eps2", "oracle_eps2_complex_step", "oracle_jvp", "oracle_limit_face",
-                 "oracle_musta_flux"):
+                 "oracle_musta_flux", "oracle_count_flops"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -361,3 +362,12 @@ def musta_flux(d: int, uL, uR, k: int, states: bool = False):
     F, ak, bk = np.empty(5), np.empty(5), np.empty(5)
     assert _load().oracle_musta_flux(int(d), _dp(a), _dp(b), int(k), _dp(F), _dp(ak), _dp(bk)) == 0
     return (F, ak, bk) if states else F
+
+
+def count_flops(what: str, scheme: str = "z"):
+    """{add, mul, div, sqrt} counts of one plain-formulation call: what =
+    "weno7", "weno5" (scheme z, js or linear) or "c2p"."""
+    out = (ctypes.c_longlong * 4)()
+    code = {"weno7": 0, "weno5": 1, "c2p": 2}[what]
+    assert _load().oracle_count_flops(code, {"z": 0, "js": 1, "linear": 2}[scheme], out) == 0
+    return dict(zip(("add", "mul", "div", "sqrt"), list(out)))

@@ -57,6 +57,24 @@ inline cplx cexp(const cplx& z) { return std::exp(z); }
 inline double cquarter(double x) { return std::pow(x, 0.25); }
 inline cplx cquarter(const cplx& z) { return std::pow(z, 0.25); }
 
+// A double that counts its arithmetic (adds and subtracts, multiplies,
+// divides, square roots; negation and |x| are free), for counting the work of
+// the plain formulation.  Counters are per thread.
+struct Counted {
+  double v;
+  Counted() : v(0.0) {}
+  Counted(double x) : v(x) {}  // NOLINT: implicit, so that literals mix in
+};
+thread_local long long g_flops[4];  // add, mul, div, sqrt
+inline Counted operator+(Counted a, Counted b) { ++g_flops[0]; return Counted(a.v + b.v); }
+inline Counted operator-(Counted a, Counted b) { ++g_flops[0]; return Counted(a.v - b.v); }
+inline Counted operator*(Counted a, Counted b) { ++g_flops[1]; return Counted(a.v * b.v); }
+inline Counted operator/(Counted a, Counted b) { ++g_flops[2]; return Counted(a.v / b.v); }
+inline Counted operator-(Counted a) { return Counted(-a.v); }
+inline double re(const Counted& x) { return x.v; }
+inline Counted aabs(const Counted& x) { return Counted(std::fabs(x.v)); }
+inline Counted csqrt(const Counted& x) { ++g_flops[3]; return Counted(std::sqrt(x.v)); }
+
 }  // namespace
 
 extern "C" {
@@ -1009,6 +1027,27 @@ int oracle_musta_flux(int d, const double* uL, const double* uR, int k, double* 
     if (uLk) uLk[m] = a[m];
     if (uRk) uRk[m] = b[m];
   }
+  return 0;
+}
+
+// Operation counts {adds, multiplies, divides, square roots} of one call of
+// the plain formulation: what = 0 a WENO7 reconstruction, 1 a WENO5
+// reconstruction (scheme 0 Z, 1 JS, 2 linear), 2 a conserved->primitive
+// recovery of an admissible state.
+int oracle_count_flops(int what, int scheme, long long* out4) {
+  if (what < 0 || what > 2 || scheme < 0 || scheme > 2 || !out4) return -1;
+  for (int k = 0; k < 4; ++k) g_flops[k] = 0;
+  if (what == 0) {
+    Counted a[7] = {1.0, 1.3, 0.7, 2.1, 1.9, 2.6, 2.2};
+    (void)weno7_left<Counted>(a, scheme, 1e-6, 2);
+  } else if (what == 1) {
+    Counted a[5] = {1.0, 1.3, 0.7, 2.1, 1.9};
+    (void)weno5_left<Counted>(a, scheme, 1e-6, 2);
+  } else {
+    long long fx = 0;
+    (void)cons_to_prim<Counted>(Counted(5.0), Counted(1.0), Counted(-0.5), Counted(0.3), Counted(0.8), &fx);
+  }
+  for (int k = 0; k < 4; ++k) out4[k] = g_flops[k];
   return 0;
 }
 

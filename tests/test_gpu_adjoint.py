@@ -348,3 +348,22 @@ def test_skip_n_option_is_exact_for_zero_n_adjoint():
             h.set_option(H.OPT_ADJ_SKIP_N, 2)
         finally:
             h.close()
+
+
+def test_torch_gradcheck_small():
+    """torch.autograd.gradcheck (fast mode: random projections of the Jacobian
+    against central differences of the GPU forward, eps 1e-6) of the
+    differentiable eps2 at 16^3, 3 steps."""
+    A = adjoint_mod()
+    w = small(n=(16, 16, 16), steps=3)
+    w.jets[0].x0 = (-0.4345, 0.031, 0.013)
+    pb = A.Eps2Problem(w, ckpt_every=2)
+    j = w.jets[0]
+    e0 = torch.tensor(w.prim0[0], dtype=torch.float64, device="cuda", requires_grad=True)
+    kr = torch.tensor(j.kappa_rad, dtype=torch.float64, requires_grad=True)
+    kc = torch.tensor(j.kappa_coll, dtype=torch.float64, requires_grad=True)
+    xy = torch.tensor(j.x0[:2], dtype=torch.float64, requires_grad=True)
+    ok = torch.autograd.gradcheck(lambda a, b, c, d: A.eps2(a, b, c, d, pb), (e0, kr, kc, xy), eps=1e-6,
+                                  atol=1e-9, rtol=1e-4, fast_mode=True)
+    assert ok
+    pb.h.close()
