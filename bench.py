@@ -79,8 +79,8 @@ PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3}  # MI355X vector FP64 / FP32 (packed)
 # kernel source with the given hash; reported as null once the source changes.
 # Source: profiles/stage_256cube_f64.md.
 MEASURED_TRAFFIC = {
-    ("zmarch", "f64", "tile", 256): {"kernels_sha256": "ff6c81cc63ef68be",
-                                     "read_bytes": 893480 * 2.0 * 1024, "write_bytes": 655360 * 1.0 * 1024},
+    ("zmarch", "f64", "tile", 256): {"kernels_sha256": "befa5e637ad18aa9",
+                                     "read_bytes": 893434 * 2.0 * 1024, "write_bytes": 655360 * 1.0 * 1024},
 }
 
 

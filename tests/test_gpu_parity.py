@@ -32,16 +32,16 @@ def H():
     return hydro
 
 
-def oracle_problem(w, bc=None, weno="z"):
-    return O.Problem(n=w.n, dx=w.dx, t0=w.t0, dt=w.dt, bc=tuple(bc or w.bc), weno=weno, deposit=w.deposit)
+def oracle_problem(w, bc=None, weno="z", **kw):
+    return O.Problem(n=w.n, dx=w.dx, t0=w.t0, dt=w.dt, bc=tuple(bc or w.bc), weno=weno, deposit=w.deposit, **kw)
 
 
 def oracle_jets(w):
     return [O.Jet(**j.__dict__) for j in w.jets]
 
 
-def run_oracle(w, steps, bc=None, weno="z"):
-    pb = oracle_problem(w, bc, weno)
+def run_oracle(w, steps, bc=None, weno="z", **kw):
+    pb = oracle_problem(w, bc, weno, **kw)
     U0 = O.prim_to_cons(pb, w.prim0)
     return pb, O.run(pb, U0, steps, oracle_jets(w))
 
@@ -336,13 +336,18 @@ def centred_block(prim, K, J, I, r):
     return np.ascontiguousarray(prim[:, K - r:K + r + 1, J - r:J + r + 1, I - r:I + r + 1])
 
 
-def test_paper_shape_256_sampled_cells_fp64():
-    """256^3 FP64, one step in the bench's launch configuration, checked at
-    sampled cells: one RK3 step of a cell depends only on cells within 12
-    along the axes, so the oracle run on the 25^3 block around a cell gives
-    that cell's exact result (the block's own boundary never reaches it)."""
+@pytest.mark.parametrize("opts", [{}, {"limiter": "pp"}, {"flux": "musta", "musta_k": 2}],
+                         ids=["weno-lf", "limiter", "musta"])
+def test_paper_shape_256_sampled_cells_fp64(opts):
+    """256^3 FP64, one step in the bench's launch configuration (and with the
+    limiter or MUSTA-FORCE fluxes, as `bench.py --limiter pp` / `--flux
+    musta` run them), checked at sampled cells: one RK3 step of a cell
+    depends only on cells within 12 along the axes (4 per stage, the limiter
+    and MUSTA included), so the oracle run on the 25^3 block around a cell
+    gives that cell's exact result (the block's own boundary never reaches
+    it)."""
     w = W.paper_event(2)
-    h = H().from_workload(w)
+    h = H().from_workload(w, **opts)
     h.step(1)
     U = h.U.cpu().numpy()
     jet = w.jets[0]
@@ -357,7 +362,7 @@ def test_paper_shape_256_sampled_cells_fp64():
         # jet in the block's coordinates (block centre cell sits at 0)
         shift = [(idx - 127.5) * 0.1 for idx in (I, J, K)]
         sub.jets = [W.JetSpec(x0=tuple(jet.x0[d] - shift[d] for d in range(3)), dir=jet.dir, E0=jet.E0)]
-        pb, st = run_oracle(sub, 1)
+        pb, st = run_oracle(sub, 1, **opts)
         ref = st.U[:, r, r, r]
         got = U[:, K, J, I]
         Emax = abs(ref[0])
