@@ -104,7 +104,7 @@ typedef enum { HYDRO_LIMITER_NONE = 0, HYDRO_LIMITER_PP = 1 } hydro_limiter;
 typedef enum { HYDRO_FLUX_WENO_LF = 0, HYDRO_FLUX_MUSTA = 1 } hydro_flux;
 
 typedef struct {
-  int32_t n[3];        /* cells along x, y, z >= 1; n[0] <= 810 (FP64) or 1024 (FP32),
+  int32_t n[3];        /* cells along x, y, z >= 1; n[0] <= 811 (FP64) or 1024 (FP32),
                           n[1], n[2] <= 65535 */
   double dx[3];        /* cell widths [fm], > 0 */
   double t0;           /* initial time [fm/c] */

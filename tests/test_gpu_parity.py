@@ -97,6 +97,28 @@ def test_ragged_grids_fp64(n, bc):
     assert np.all(err <= 1e-12), err
 
 
+@pytest.mark.parametrize("precision,n", [("f64", (811, 3, 2)), ("f32", (1024, 2, 3))])
+def test_largest_x_rows(precision, n):
+    """The longest x rows the x-face kernel takes (811 cells FP64, 1024 FP32:
+    one row of split fluxes in 64 KiB of LDS) against the oracle; a length
+    one beyond is refused."""
+    w = W.small_event(3, n=n, steps=2)
+    w.jets[0].x0 = (-30.0137, 0.0123, -0.0071)
+    pb, st = run_oracle(w, 2, bc=("outflow", "periodic", "periodic"))
+    h = run_gpu(w, 2, precision=precision, bc=("outflow", "periodic", "periodic"))
+    if precision == "f64":
+        err = rel_linf(h.U.cpu().numpy(), st.U)
+        report("grid %s" % (n,), err)
+        assert np.all(err <= 1e-12), err
+    else:
+        e_err, v_err = fp32_errors(h.U.cpu().numpy(), st.U, pb)
+        print("FP32 %s: rel L2 e %.2e |v| %.2e" % (n, e_err, v_err), flush=True)
+        assert e_err <= 1e-5 and v_err <= 1e-5
+    h.close()
+    big = H().make_config((n[0] + 1, 2, 2), precision=precision)
+    assert H().workspace_bytes(big, 0) == 0
+
+
 @pytest.mark.parametrize("weno", ["js", "linear"])
 def test_weno_variants_fp64(weno):
     w = W.small_event(4, n=(24, 20, 28), steps=4)
