@@ -113,7 +113,7 @@ __device__ __forceinline__ double rcp_approx<double>(double x) {
 template <class R>
 __device__ __forceinline__ R smoothness(R D1, R D2, R D3, R h, R m, R g, R eps) {
   const R sk = fma(m, D3, fma(h, D2, D1));
-  const R ck = fma(g, D3, D2);
+  const R ck = (g == R(0)) ? D2 : fma(g, D3, D2);  // g is a literal: no select survives
   return fma(sk, sk, fma(R(13.0 / 12.0) * ck, ck, fma(R(781.0 / 720.0) * D3, D3, eps)));
 }
 
@@ -126,9 +126,12 @@ __device__ __forceinline__ double rcp_nr(double x) {
   return r;
 }
 
-// num / den from one reciprocal plus a residual correction.
+// num / den from one reciprocal plus a residual correction: the estimate
+// (~23 bits) after one Newton step (~46 bits) gives q = num r to ~2^-46, and
+// q + (num - den q) r squares that error away (below the rounding of q).
 __device__ __forceinline__ double div_nr(double num, double den) {
-  const double r = rcp_nr(den);
+  double r = __builtin_amdgcn_rcp(den);
+  r = fma(fma(-den, r, 1.0), r, r);
   const double q = num * r;
   return fma(fma(-den, q, num), r, q);
 }
@@ -152,14 +155,20 @@ __device__ __forceinline__ R weno5(R b0, R b1, R b2, R b3, R b4, R eps) {
   if (sizeof(R) == 8) {
     // common denominator: with B_k = b_k^2, WENO-Z d_k (B_k + tau^2) prod_{j!=k} B_j,
     // Jiang-Shu d_k prod_{j!=k} B_j
+    // (WENO-Z: (B_0 + tau^2) B_1 = B_0 B_1 + tau^2 B_1, and so on.)
     const R B0 = be0 * be0, B1 = be1 * be1, B2 = be2 * be2;
-    R A0 = B1 * B2, A1 = B0 * B2, A2 = B0 * B1;
+    const R P01 = B0 * B1;
+    R A0, A1, A2;
     if (S == kWeno5Z) {
       const R tau = fabs(be0 - be2);
       const R t2 = tau * tau;
-      A0 = (B0 + t2) * A0;
-      A1 = (B1 + t2) * A1;
-      A2 = (B2 + t2) * A2;
+      A0 = fma(t2, B1, P01) * B2;
+      A1 = fma(t2, B0, P01) * B2;
+      A2 = (B2 + t2) * P01;
+    } else {
+      A0 = B1 * B2;
+      A1 = B0 * B2;
+      A2 = P01;
     }
     const R num = fma(A2, r2, fma(A1, r1, A0 * r0));
     const R den = fma(A2, R(0.3), fma(A1, R(0.6), A0 * R(0.1)));
@@ -209,16 +218,22 @@ __device__ __forceinline__ R weno7(R a0, R a1, R a2, R a3, R a4, R a5, R a6, R e
     // Weights over a common denominator: with B_k = b_k^2 the WENO-Z weight
     // d_k (1 + tau^2/B_k) is proportional to d_k (B_k + tau^2) prod_{j!=k} B_j,
     // the Jiang-Shu weight d_k/B_k to d_k prod_{j!=k} B_j.  One division.
+    // (WENO-Z: (B_0 + tau^2) B_1 = B_0 B_1 + tau^2 B_1, and so on, one fma each.)
     const R B0 = b0 * b0, B1 = b1 * b1, B2 = b2 * b2, B3 = b3 * b3;
     const R P01 = B0 * B1, P23 = B2 * B3;
-    R A0 = B1 * P23, A1 = B0 * P23, A2 = P01 * B3, A3 = P01 * B2;
+    R A0, A1, A2, A3;
     if (S == kWenoZ) {
       const R tau = fabs(fma(R(3), b1 - b2, b0 - b3));
       const R t2 = tau * tau;
-      A0 = (B0 + t2) * A0;
-      A1 = (B1 + t2) * A1;
-      A2 = (B2 + t2) * A2;
-      A3 = (B3 + t2) * A3;
+      A0 = fma(t2, B1, P01) * P23;
+      A1 = fma(t2, B0, P01) * P23;
+      A2 = fma(t2, B3, P23) * P01;
+      A3 = fma(t2, B2, P23) * P01;
+    } else {
+      A0 = B1 * P23;
+      A1 = B0 * P23;
+      A2 = P01 * B3;
+      A3 = P01 * B2;
     }
     const R num = fma(A3, r3, fma(A2, r2, fma(A1, r1, A0 * r0)));
     const R den = fma(A3, R(4.0 / 35.0), fma(A2, R(18.0 / 35.0), fma(A1, R(12.0 / 35.0), A0 * R(1.0 / 35.0))));
