@@ -87,9 +87,9 @@ __device__ __forceinline__ void split_flux(const R u[5], const PrimV& p, R Fp[5]
 
 // ---------------------------------------------------------------------------
 // WENO7 value at x_{i+1/2} from the left, a0..a6 = a_{i-3}..a_{i+3}.
-// The candidates q_k of the 4-point stencils enter as d_k (q_k - a_{i}),
+// The candidates q_k of the 4-point stencils enter as 35 d_k (q_k - a_{i}),
 // d = (1, 12, 18, 4)/35, written with the first differences, and the result
-// is a_i + sum w_k d_k (q_k - a_i) / sum w_k d_k.  Smoothness indicators (Jiang-Shu: the
+// is a_i + sum w_k 35 d_k (q_k - a_i) / sum w_k 35 d_k.  Smoothness indicators (Jiang-Shu: the
 // integral over cell i of the squared derivatives of stencil k's cubic) are
 // evaluated from the nested differences D1, D2, D3 of the stencil values:
 //   b_k = s_k^2 + 13/12 c_k^2 + 781/720 D3_k^2 + eps,
@@ -143,10 +143,11 @@ __device__ __forceinline__ double div_nr(double num, double den) {
 template <class R, int S>
 __device__ __forceinline__ R weno5(R b0, R b1, R b2, R b3, R b4, R eps) {
   const R e0 = b1 - b0, e1 = b2 - b1, e2 = b3 - b2, e3 = b4 - b3;
-  const R r0 = fma(R(5.0 / 60.0), e1, R(-2.0 / 60.0) * e0);
-  const R r1 = fma(R(2.0 / 10.0), e2, R(1.0 / 10.0) * e1);
-  const R r2 = fma(R(-1.0 / 20.0), e3, R(4.0 / 20.0) * e2);
-  if (S == kWeno5Linear) return b2 + ((r0 + r1) + r2);
+  // candidates as 10 d_k (q_k - b2) (the 10 cancels against sum 10 w_k d_k)
+  const R r0 = fma(R(5.0 / 6.0), e1, R(-1.0 / 3.0) * e0);
+  const R r1 = fma(R(2.0), e2, e1);
+  const R r2 = fma(R(-0.5), e3, R(2.0) * e2);
+  if (S == kWeno5Linear) return fma((r0 + r1) + r2, R(0.1), b2);
   const R f0 = e1 - e0, f1 = e2 - e1, f2 = e3 - e2;
   const R s0 = fma(R(1.5), f0, e0), s1 = fma(R(0.5), f1, e1), s2 = fma(R(-0.5), f2, e2);
   const R be0 = fma(s0, s0, fma(R(13.0 / 12.0) * f0, f0, eps));
@@ -171,7 +172,7 @@ __device__ __forceinline__ R weno5(R b0, R b1, R b2, R b3, R b4, R eps) {
       A2 = P01;
     }
     const R num = fma(A2, r2, fma(A1, r1, A0 * r0));
-    const R den = fma(A2, R(0.3), fma(A1, R(0.6), A0 * R(0.1)));
+    const R den = fma(A2, R(3.0), fma(A1, R(6.0), A0));
     return b2 + (R)div_nr((double)num, (double)den);
   } else {
     const R i0 = rcp_approx<R>(be0), i1 = rcp_approx<R>(be1), i2 = rcp_approx<R>(be2);
@@ -188,7 +189,7 @@ __device__ __forceinline__ R weno5(R b0, R b1, R b2, R b3, R b4, R eps) {
       w2 = i2 * i2;
     }
     const R num = fma(w2, r2, fma(w1, r1, w0 * r0));
-    const R den = fma(w2, R(0.3), fma(w1, R(0.6), w0 * R(0.1)));
+    const R den = fma(w2, R(3.0), fma(w1, R(6.0), w0));
     return fma(num, rcp_approx<R>(den), b2);
   }
 }
@@ -200,12 +201,13 @@ __device__ __forceinline__ R weno7(R a0, R a1, R a2, R a3, R a4, R a5, R a6, R e
   if (S >= kWeno5Z) return weno5<R, S>(a1, a2, a3, a4, a5, eps);
   // nested differences of the seven values
   const R e0 = a1 - a0, e1 = a2 - a1, e2 = a3 - a2, e3 = a4 - a3, e4 = a5 - a4, e5 = a6 - a5;
-  // candidates as d_k (q_k - a3), from the differences
-  const R r0 = fma(R(13.0 / 420.0), e2, fma(R(-10.0 / 420.0), e1, R(3.0 / 420.0) * e0));
-  const R r1 = fma(R(3.0 / 35.0), e3, fma(R(4.0 / 35.0), e2, R(-1.0 / 35.0) * e1));
-  const R r2 = fma(R(-3.0 / 70.0), e4, fma(R(18.0 / 70.0), e3, R(3.0 / 70.0) * e2));
-  const R r3 = fma(R(1.0 / 105.0), e5, fma(R(-4.0 / 105.0), e4, R(9.0 / 105.0) * e3));
-  if (S == kWenoLinear) return a3 + ((r0 + r1) + (r2 + r3));
+  // candidates as 35 d_k (q_k - a3), from the differences (the factor 35
+  // cancels against the weights' denominator sum 35 w_k d_k)
+  const R r0 = fma(R(13.0 / 12.0), e2, fma(R(-10.0 / 12.0), e1, R(3.0 / 12.0) * e0));
+  const R r1 = fma(R(3.0), e3, fma(R(4.0), e2, -e1));
+  const R r2 = fma(R(-1.5), e4, fma(R(9.0), e3, R(1.5) * e2));
+  const R r3 = fma(R(1.0 / 3.0), e5, fma(R(-4.0 / 3.0), e4, R(3.0) * e3));
+  if (S == kWenoLinear) return fma((r0 + r1) + (r2 + r3), R(1.0 / 35.0), a3);
 
   const R f0 = e1 - e0, f1 = e2 - e1, f2 = e3 - e2, f3 = e4 - e3, f4 = e5 - e4;
   const R g0 = f1 - f0, g1 = f2 - f1, g2 = f3 - f2, g3 = f4 - f3;
@@ -236,7 +238,7 @@ __device__ __forceinline__ R weno7(R a0, R a1, R a2, R a3, R a4, R a5, R a6, R e
       A3 = P01 * B2;
     }
     const R num = fma(A3, r3, fma(A2, r2, fma(A1, r1, A0 * r0)));
-    const R den = fma(A3, R(4.0 / 35.0), fma(A2, R(18.0 / 35.0), fma(A1, R(12.0 / 35.0), A0 * R(1.0 / 35.0))));
+    const R den = fma(A3, R(4.0), fma(A2, R(18.0), fma(A1, R(12.0), A0)));
     return a3 + (R)div_nr((double)num, (double)den);
   } else {
     const R i0 = rcp_approx<R>(b0), i1 = rcp_approx<R>(b1), i2 = rcp_approx<R>(b2), i3 = rcp_approx<R>(b3);
@@ -255,7 +257,7 @@ __device__ __forceinline__ R weno7(R a0, R a1, R a2, R a3, R a4, R a5, R a6, R e
       w3 = i3 * i3;
     }
     const R num = fma(w3, r3, fma(w2, r2, fma(w1, r1, w0 * r0)));
-    const R den = fma(w3, R(4.0 / 35.0), fma(w2, R(18.0 / 35.0), fma(w1, R(12.0 / 35.0), w0 * R(1.0 / 35.0))));
+    const R den = fma(w3, R(4.0), fma(w2, R(18.0), fma(w1, R(12.0), w0)));
     return fma(num, rcp_approx<R>(den), a3);
   }
 }
