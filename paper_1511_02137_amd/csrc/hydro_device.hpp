@@ -26,6 +26,39 @@ __device__ __forceinline__ void load5(const R* __restrict__ W, long long nc, lon
 }
 
 // ---------------------------------------------------------------------------
+// Reciprocal for FP64: hardware estimate, two Newton steps (quadratic
+// convergence from the estimate's ~23 bits to full precision).
+__device__ __forceinline__ double rcp_nr(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  r = fma(fma(-x, r, 1.0), r, r);
+  r = fma(fma(-x, r, 1.0), r, r);
+  return r;
+}
+
+// num / den from one reciprocal plus a residual correction: the estimate
+// (~23 bits) after one Newton step (~46 bits) gives q = num r to ~2^-46, and
+// q + (num - den q) r squares that error away (below the rounding of q).
+__device__ __forceinline__ double div_nr(double num, double den) {
+  double r = __builtin_amdgcn_rcp(den);
+  r = fma(fma(-den, r, 1.0), r, r);
+  const double q = num * r;
+  return fma(fma(-den, q, num), r, q);
+}
+
+// sqrt(x) for normal x > 0: reciprocal square root estimate, two coupled
+// Newton iterations for sqrt(x) and 1/(2 sqrt(x)), one residual correction.
+__device__ __forceinline__ double sqrt_nr(double x) {
+  const double y = __builtin_amdgcn_rsq(x);
+  double g = x * y, h = 0.5 * y;
+  double r = fma(-g, h, 0.5);
+  g = fma(g, r, g);
+  h = fma(h, r, h);
+  r = fma(-g, h, 0.5);
+  g = fma(g, r, g);
+  h = fma(h, r, h);
+  return fma(fma(-g, g, x), h, g);
+}
+
 // Conserved -> primitive for p = e/3 (FP64): e = 3(E^2 - M^2)/(E + sqrt(4E^2
 // - 3M^2)), v = M/(E + e/3).  Non-admissible cells are fixed up for the
 // primitive calculation only (E <= 1e-12: vacuum at rest; |M| >= (1-1e-10) E:
@@ -52,8 +85,8 @@ __device__ __forceinline__ PrimV c2p(double E, double Mx, double My, double Mz, 
     Mz = Mz * sc;
     M2 = Mx * Mx + My * My + Mz * Mz;
   }
-  const double e = 3.0 * (E * E - M2) / (E + sqrt(4.0 * E * E - 3.0 * M2));
-  const double iW = 1.0 / (E + e * (1.0 / 3.0));
+  const double e = div_nr(3.0 * (E * E - M2), E + sqrt_nr(4.0 * E * E - 3.0 * M2));
+  const double iW = rcp_nr(E + e * (1.0 / 3.0));
   r.e = e;
   r.v[0] = Mx * iW;
   r.v[1] = My * iW;
@@ -115,25 +148,6 @@ __device__ __forceinline__ R smoothness(R D1, R D2, R D3, R h, R m, R g, R eps) 
   const R sk = fma(m, D3, fma(h, D2, D1));
   const R ck = (g == R(0)) ? D2 : fma(g, D3, D2);  // g is a literal: no select survives
   return fma(sk, sk, fma(R(13.0 / 12.0) * ck, ck, fma(R(781.0 / 720.0) * D3, D3, eps)));
-}
-
-// Reciprocal for FP64: hardware estimate, two Newton steps (quadratic
-// convergence from the estimate's ~23 bits to full precision).
-__device__ __forceinline__ double rcp_nr(double x) {
-  double r = __builtin_amdgcn_rcp(x);
-  r = fma(fma(-x, r, 1.0), r, r);
-  r = fma(fma(-x, r, 1.0), r, r);
-  return r;
-}
-
-// num / den from one reciprocal plus a residual correction: the estimate
-// (~23 bits) after one Newton step (~46 bits) gives q = num r to ~2^-46, and
-// q + (num - den q) r squares that error away (below the rounding of q).
-__device__ __forceinline__ double div_nr(double num, double den) {
-  double r = __builtin_amdgcn_rcp(den);
-  r = fma(fma(-den, r, 1.0), r, r);
-  const double q = num * r;
-  return fma(fma(-den, q, num), r, q);
 }
 
 // WENO5 value at x_{i+1/2} from the left, b0..b4 = a_{i-2}..a_{i+2}, in the
