@@ -112,9 +112,10 @@ __device__ __forceinline__ void split_flux(const R u[5], const PrimV& p, R Fp[5]
   f[3] = (AX == 2) ? u[3] * vd + pr : u[3] * vd;
   f[4] = u[4] * vd;
 #pragma unroll
-  for (int c = 0; c < 5; ++c) {
-    Fp[c] = R(0.5) * (f[c] + u[c]);
-    Fm[c] = R(0.5) * (f[c] - u[c]);
+  for (int c = 0; c < 5; ++c) {  // (f +- u)/2 with one rounding: u/2 is exact
+    const R hu = R(0.5) * u[c];
+    Fp[c] = fma(R(0.5), f[c], hu);
+    Fm[c] = fma(R(0.5), f[c], -hu);
   }
 }
 
