@@ -76,12 +76,22 @@ PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3}  # MI355X vector FP64 / FP32 (packed)
 
 # HBM bytes per launch from rocprofv3 FETCH_SIZE / WRITE_SIZE runs (KiB per
 # dispatch, scaled by a 1 GiB plain copy: read x2.0, write x1.0), for the
-# kernel source with the given hash; reported as null once the source changes.
-# Source: profiles/stage_256cube_f64.md.
+# kernel sources with the given hash (KERNEL_SOURCES); reported as null once
+# any of them changes.  Source: profiles/stage_256cube_f64.md.
 MEASURED_TRAFFIC = {
-    ("zmarch", "f64", "tile", 256): {"kernels_sha256": "befa5e637ad18aa9",
-                                     "read_bytes": 893434 * 2.0 * 1024, "write_bytes": 655360 * 1.0 * 1024},
+    ("zmarch", "f64", "tile", 256): {"kernels_sha256": "eb27346db1d42a6c",
+                                     "read_bytes": 893724 * 2.0 * 1024, "write_bytes": 655360 * 1.0 * 1024},
 }
+KERNEL_SOURCES = ("hydro_kernels.hip", "hydro_device.hpp", "hydro_internal.hpp")
+
+
+def kernels_sha256() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for name in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_1511_02137_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
 
 
 def cpu_baseline(w, target_s: float):
@@ -314,11 +324,8 @@ def main():
     traffic = None
     rec = (MEASURED_TRAFFIC.get((dom, args.precision, args.yz, args.n))
            if args.weno == "z" and args.limiter == "none" and args.flux == "weno" else None)
-    if rec is not None:
-        import hashlib
-        src = os.path.join(ROOT, "paper_1511_02137_amd", "csrc", "hydro_kernels.hip")
-        if hashlib.sha256(open(src, "rb").read()).hexdigest()[:16] == rec["kernels_sha256"]:
-            traffic = rec["read_bytes"] + rec["write_bytes"]
+    if rec is not None and kernels_sha256() == rec["kernels_sha256"]:
+        traffic = rec["read_bytes"] + rec["write_bytes"]
     roofline = {"bound": "alu", "kernel": dom, "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
                 "frac": achieved / peak, "traffic": traffic,
                 "algorithmic_bytes": BYTES_PER_CELL[dom] * (8 if args.precision == "f64" else 4) * nc,
