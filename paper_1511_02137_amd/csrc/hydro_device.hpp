@@ -413,11 +413,25 @@ __device__ __forceinline__ double pp_side(const PPHalf& s0, const PPHalf& s1) {
 // at a time, so that few values stay live.
 template <class R, class Get>
 __device__ __forceinline__ void pp_limit(R H[5], Get get, double mu) {
-  const PPHalf a1 = pp_half<R>(H, get, mu, 0, false);
-  const PPHalf b1 = pp_half<R>(H, get, mu, 1, false);
-  if (pp_inside(a1.e, a1.m2, a1.n) && pp_inside(b1.e, b1.m2, b1.n)) return;
-  const double ta = pp_side(pp_half<R>(H, get, mu, 0, true), a1);
-  const double tb = pp_side(pp_half<R>(H, get, mu, 1, true), b1);
+  bool inside;
+  __asm__ __volatile__("" ::: "memory");
+  {
+    const PPHalf a1 = pp_half<R>(H, get, mu, 0, false);
+    inside = pp_inside(a1.e, a1.m2, a1.n);
+  }
+  __asm__ __volatile__("" ::: "memory");
+  if (inside) {
+    const PPHalf b1 = pp_half<R>(H, get, mu, 1, false);
+    inside = pp_inside(b1.e, b1.m2, b1.n);
+  }
+  if (inside) return;
+  // rarely taken: each side again, with the first-order flux beside it.  The
+  // empty asm with a memory clobber makes the compiler read the split fluxes
+  // again here instead of keeping them in registers across the common path.
+  __asm__ __volatile__("" ::: "memory");
+  const double ta = pp_side(pp_half<R>(H, get, mu, 0, true), pp_half<R>(H, get, mu, 0, false));
+  __asm__ __volatile__("" ::: "memory");
+  const double tb = pp_side(pp_half<R>(H, get, mu, 1, true), pp_half<R>(H, get, mu, 1, false));
   const double th = fmin(ta, tb);
 #pragma unroll
   for (int c = 0; c < 5; ++c) {
