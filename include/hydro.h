@@ -181,7 +181,9 @@ int hydro_rk3_step(hydro_ctx* ctx, void* U, int nsteps, void* stream);
 
 /* Right-hand side of one stage, L(U) = D(U) + S(U) at time t, into L
  * (device, same layout and type as U, not aliasing U).  Jets deposit with
- * their current energies; E_jet and the ledger are not advanced. */
+ * their current energies; E_jet and the ledger are not advanced.  With
+ * HYDRO_LIMITER_PP the face fluxes are those limited for a forward-Euler
+ * step of length cfg.dt (the limiter depends on dt). */
 int hydro_rhs(hydro_ctx* ctx, const void* U, double t, void* L, void* stream);
 
 /* Primitive fields of U: prim [6][nz][ny][nx] of U's type: e, vx, vy, vz,
