@@ -106,3 +106,21 @@ def test_null_context_is_rejected(lib):
     assert lib.hydro_rk3_step(None, ctypes.c_void_p(256), 1, None) == H.HYDRO_EINVAL
     assert lib.hydro_add_jet(None, None, None) == H.HYDRO_EINVAL
     lib.hydro_destroy(None)
+
+
+def test_product_fails_loudly_without_library_or_gpu(tmp_path):
+    """No fallback: a missing libhydro.so raises, and so does a context
+    without a GPU (checked in fresh interpreters; the second check only
+    where torch sees no GPU)."""
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    code = ("from paper_1511_02137_amd import hydro as H\n"
+            "try:\n    H.load_library(%r)\nexcept RuntimeError as e:\n    print('raised', e)\n" % str(tmp_path / "none.so"))
+    r = subprocess.run([sys.executable, "-c", code], cwd=root, capture_output=True, text=True, timeout=300)
+    assert "raised libhydro.so is not built" in r.stdout, r.stdout + r.stderr
+    code = ("import torch\nfrom paper_1511_02137_amd import hydro as H\n"
+            "if torch.cuda.is_available():\n    print('gpu present')\nelse:\n"
+            "    try:\n        H.Hydro(H.make_config((8, 8, 8)), None)\n"
+            "    except RuntimeError as e:\n        print('raised', e)\n")
+    r = subprocess.run([sys.executable, "-c", code], cwd=root, capture_output=True, text=True, timeout=300)
+    assert "gpu present" in r.stdout or "raised libhydro needs a GPU" in r.stdout, r.stdout + r.stderr
