@@ -122,6 +122,14 @@ def cpu_baseline(w, target_s: float):
     p1 = max(1, min(planes, int(planes * 0.1 * target_s / max(t * cores, 1e-3))))
     t1 = run_slab(p1)
     O.set_threads(cores)
+    # the whole 32^3 x 10-step small event on all cores
+    from paper_1511_02137_amd import workloads as W
+    ws = W.small_event(1)
+    pbs = O.Problem(n=ws.n, dx=ws.dx, t0=ws.t0, dt=ws.dt, bc=ws.bc)
+    Us = O.prim_to_cons(pbs, ws.prim0)
+    ts = time.perf_counter()
+    O.run(pbs, Us, ws.steps, [O.Jet(**j.__dict__) for j in ws.jets])
+    ts = time.perf_counter() - ts
     model = ""
     try:
         for line in open("/proc/cpuinfo"):
@@ -139,6 +147,8 @@ def cpu_baseline(w, target_s: float):
                   "%.1f s wall" % (w.n[0], w.n[1], planes, w.name, t),
         "single_core_value": w.n[0] * w.n[1] * p1 * 3 / t1,
         "single_core_sample": "the central %dx%dx%d z-slab, one step, %.1f s wall" % (w.n[0], w.n[1], p1, t1),
+        "small_event_run_s": ts,
+        "small_event_run": "%s, %d steps, all cores" % (ws.name, ws.steps),
         "host_cpu": model, "host_logical_cpus": os.cpu_count(),
     }
 
