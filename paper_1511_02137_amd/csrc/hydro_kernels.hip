@@ -80,14 +80,28 @@ __device__ __forceinline__ void xrows_body(const StageArgs<R>& a, long long row0
       sFp[c * P + x + 4] = Fp[c];
       sFm[c * P + x + 4] = Fm[c];
     }
-    for (int g = 0; g < 8; ++g) {
-      const int j = g < 4 ? g : nx + g;  // ghost slots 0..3 and nx+4..nx+7
-      if (map_idx(j - 4, nx, a.g.bc[0]) == x) {
+    // ghost slots 0..3 and nx+4..nx+7, each filled by the lane whose cell it
+    // copies: outflow, the edge lanes; periodic, the lanes four from the far
+    // end (rows of at least 8 cells; shorter rows take the general map)
+    auto put = [&](int j) {
 #pragma unroll
-        for (int c = 0; c < 5; ++c) {
-          sFp[c * P + j] = Fp[c];
-          sFm[c * P + j] = Fm[c];
-        }
+      for (int c = 0; c < 5; ++c) {
+        sFp[c * P + j] = Fp[c];
+        sFm[c * P + j] = Fm[c];
+      }
+    };
+    if (nx >= 8) {
+      if (a.g.bc[0]) {
+        if (x >= nx - 4) put(x - nx + 4);
+        if (x < 4) put(nx + 4 + x);
+      } else if (x == 0 || x == nx - 1) {
+        const int j0 = x == 0 ? 0 : nx + 4;
+        for (int k = 0; k < 4; ++k) put(j0 + k);
+      }
+    } else {
+      for (int g = 0; g < 8; ++g) {
+        const int j = g < 4 ? g : nx + g;
+        if (map_idx(j - 4, nx, a.g.bc[0]) == x) put(j);
       }
     }
   }
