@@ -211,26 +211,41 @@ __device__ __forceinline__ R weno5(R b0, R b1, R b2, R b3, R b4, R eps) {
 
 // Schemes kWeno5*: the 5th-order reconstruction from the middle five values
 // (a_{i-2}..a_{i+2}) of the same 7-point window.
+// The WENO7 value in two parts: the front (candidates and smoothness
+// indicators) and the back (weights and the normalised combination).
+template <class R>
+struct W7Front {
+  R a3, r0, r1, r2, r3, b0, b1, b2, b3;
+};
+
 template <class R, int S>
-__device__ __forceinline__ R weno7(R a0, R a1, R a2, R a3, R a4, R a5, R a6, R eps) {
-  if (S >= kWeno5Z) return weno5<R, S>(a1, a2, a3, a4, a5, eps);
+__device__ __forceinline__ W7Front<R> weno7_front(R a0, R a1, R a2, R a3, R a4, R a5, R a6, R eps) {
+  W7Front<R> w;
+  w.a3 = a3;
   // nested differences of the seven values
   const R e0 = a1 - a0, e1 = a2 - a1, e2 = a3 - a2, e3 = a4 - a3, e4 = a5 - a4, e5 = a6 - a5;
   // candidates as 35 d_k (q_k - a3), from the differences (the factor 35
   // cancels against the weights' denominator sum 35 w_k d_k)
-  const R r0 = fma(R(13.0 / 12.0), e2, fma(R(-10.0 / 12.0), e1, R(3.0 / 12.0) * e0));
-  const R r1 = fma(R(3.0), e3, fma(R(4.0), e2, -e1));
-  const R r2 = fma(R(-1.5), e4, fma(R(9.0), e3, R(1.5) * e2));
-  const R r3 = fma(R(1.0 / 3.0), e5, fma(R(-4.0 / 3.0), e4, R(3.0) * e3));
-  if (S == kWenoLinear) return fma((r0 + r1) + (r2 + r3), R(1.0 / 35.0), a3);
+  w.r0 = fma(R(13.0 / 12.0), e2, fma(R(-10.0 / 12.0), e1, R(3.0 / 12.0) * e0));
+  w.r1 = fma(R(3.0), e3, fma(R(4.0), e2, -e1));
+  w.r2 = fma(R(-1.5), e4, fma(R(9.0), e3, R(1.5) * e2));
+  w.r3 = fma(R(1.0 / 3.0), e5, fma(R(-4.0 / 3.0), e4, R(3.0) * e3));
+  if (S == kWenoLinear) return w;
 
   const R f0 = e1 - e0, f1 = e2 - e1, f2 = e3 - e2, f3 = e4 - e3, f4 = e5 - e4;
   const R g0 = f1 - f0, g1 = f2 - f1, g2 = f3 - f2, g3 = f4 - f3;
-  const R b0 = smoothness<R>(e0, f0, g0, R(2.5), R(11.0 / 6.0), R(2), eps);
-  const R b1 = smoothness<R>(e1, f1, g1, R(1.5), R(1.0 / 3.0), R(1), eps);
-  const R b2 = smoothness<R>(e2, f2, g2, R(0.5), R(-1.0 / 6.0), R(0), eps);
-  const R b3 = smoothness<R>(e3, f3, g3, R(-0.5), R(1.0 / 3.0), R(-1), eps);
+  w.b0 = smoothness<R>(e0, f0, g0, R(2.5), R(11.0 / 6.0), R(2), eps);
+  w.b1 = smoothness<R>(e1, f1, g1, R(1.5), R(1.0 / 3.0), R(1), eps);
+  w.b2 = smoothness<R>(e2, f2, g2, R(0.5), R(-1.0 / 6.0), R(0), eps);
+  w.b3 = smoothness<R>(e3, f3, g3, R(-0.5), R(1.0 / 3.0), R(-1), eps);
+  return w;
+}
 
+template <class R, int S>
+__device__ __forceinline__ R weno7_back(const W7Front<R>& w) {
+  const R a3 = w.a3, r0 = w.r0, r1 = w.r1, r2 = w.r2, r3 = w.r3;
+  if (S == kWenoLinear) return fma((r0 + r1) + (r2 + r3), R(1.0 / 35.0), a3);
+  const R b0 = w.b0, b1 = w.b1, b2 = w.b2, b3 = w.b3;
   if (sizeof(R) == 8) {
     // Weights over a common denominator: with B_k = b_k^2 the WENO-Z weight
     // d_k (1 + tau^2/B_k) is proportional to d_k (B_k + tau^2) prod_{j!=k} B_j,
@@ -275,6 +290,33 @@ __device__ __forceinline__ R weno7(R a0, R a1, R a2, R a3, R a4, R a5, R a6, R e
     const R den = fma(w3, R(4.0), fma(w2, R(18.0), fma(w1, R(12.0), w0)));
     return fma(num, rcp_approx<R>(den), a3);
   }
+}
+
+template <class R, int S>
+__device__ __forceinline__ R weno7(R a0, R a1, R a2, R a3, R a4, R a5, R a6, R eps) {
+  if (S >= kWeno5Z) return weno5<R, S>(a1, a2, a3, a4, a5, eps);
+  return weno7_back<R, S>(weno7_front<R, S>(a0, a1, a2, a3, a4, a5, a6, eps));
+}
+
+// Two neighbouring reconstructions from the eight values v0..v7: lo from
+// v0..v6, hi from v1..v7, each by exactly the arithmetic of weno7.  Their
+// shared differences are formed once; the fronts of both come first and the
+// backs one after the other, which keeps fewer values live than interleaving
+// the two.
+template <class R, int S>
+__device__ __forceinline__ void weno7_pair(R v0, R v1, R v2, R v3, R v4, R v5, R v6, R v7, R eps, R& lo,
+                                           R& hi) {
+  if (S >= kWeno5Z) {
+    lo = weno5<R, S>(v1, v2, v3, v4, v5, eps);
+    hi = weno5<R, S>(v2, v3, v4, v5, v6, eps);
+    return;
+  }
+  const W7Front<R> wl = weno7_front<R, S>(v0, v1, v2, v3, v4, v5, v6, eps);
+  const W7Front<R> wh = weno7_front<R, S>(v1, v2, v3, v4, v5, v6, v7, eps);
+  __builtin_amdgcn_sched_barrier(0);
+  lo = weno7_back<R, S>(wl);
+  __builtin_amdgcn_sched_barrier(0);
+  hi = weno7_back<R, S>(wh);
 }
 
 // Face flux from the 8-point window Fp/Fm[m] = split fluxes at i-3+m:

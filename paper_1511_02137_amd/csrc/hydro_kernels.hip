@@ -10,8 +10,9 @@
 // Work split (all kernels of a stage run on one stream):
 //   k_xface   one workgroup per group of whole x-rows.  Each lane recovers
 //             primitives for its cell, stores the split x-fluxes of the row
-//             plus 4+4 ghost cells
-//             in LDS, reconstructs its left face and writes the x-divergence.
+//             plus 4+4 ghost cells in LDS, reconstructs one split of two
+//             neighbouring faces (or both splits of its left face) and
+//             writes the x-divergence.
 //   k_xbound  the right boundary face of every row (outflow x only).
 //   k_march   lanes along x (coalesced), each lane marches along y or z over
 //             a segment, keeping the split fluxes of the 8-point stencil in
@@ -35,9 +36,10 @@ namespace hydro {
 // ...; fewer at the end of the grid).  LDS per row: the split fluxes of its nx
 // cells and 8 ghost slots (slot j holds padded position j - 4), then the face
 // values.  One lane per cell: it recovers its cell, stores the split fluxes
-// (also into every ghost slot that copies the cell), reconstructs the cell's
-// left face and forms the divergence; the outflow right face of the last cell
-// is added by k_xbound.
+// (also into every ghost slot that copies the cell), reconstructs faces
+// (rows of even length: lane 2q + h the split h of faces 2q - 1/2 and
+// 2q + 1/2; otherwise the cell's left face) and forms the divergence; the
+// outflow right face of the last cell is added by k_xbound.
 // What the face kernels keep per point: the Lax-Friedrichs split fluxes
 // (F+, F-), or with MUSTA-FORCE the conserved values themselves (in the F+
 // slots; no recovery needed).
@@ -55,7 +57,7 @@ __device__ __forceinline__ void point_values(const R u[5], R Fp[5], R Fm[5], uns
   }
 }
 
-template <class R, int S>
+template <class R, int S, bool PAIRS>
 __device__ __forceinline__ void xrows_body(const StageArgs<R>& a, long long row0, int rpi, R* s) {
   const int nx = a.g.n[0];
   const int P = nx + 8;
@@ -69,6 +71,11 @@ __device__ __forceinline__ void xrows_body(const StageArgs<R>& a, long long row0
   R* sFp = s + (size_t)r * 10 * P;
   R* sFm = sFp + 5 * P;
   unsigned fix = 0;
+  // Plain WENO faces of rows with an even number of cells are taken in
+  // pairs (as in the y/z tiles); the F- points are then stored in reverse
+  // slot order.
+  const bool pair = PAIRS && (S & (kPP | kMusta)) == 0 && (nx & 1) == 0;
+  const int mrev = pair ? P - 1 : 0, msgn = pair ? -1 : 1;  // F- slot j at mrev + msgn j
 
   if (act) {
     R u[5];
@@ -78,7 +85,7 @@ __device__ __forceinline__ void xrows_body(const StageArgs<R>& a, long long row0
 #pragma unroll
     for (int c = 0; c < 5; ++c) {
       sFp[c * P + x + 4] = Fp[c];
-      sFm[c * P + x + 4] = Fm[c];
+      sFm[c * P + mrev + msgn * (x + 4)] = Fm[c];
     }
     // ghost slots 0..3 and nx+4..nx+7, each filled by the lane whose cell it
     // copies: outflow, the edge lanes; periodic, the lanes four from the far
@@ -87,7 +94,7 @@ __device__ __forceinline__ void xrows_body(const StageArgs<R>& a, long long row0
 #pragma unroll
       for (int c = 0; c < 5; ++c) {
         sFp[c * P + j] = Fp[c];
-        sFm[c * P + j] = Fm[c];
+        sFm[c * P + mrev + msgn * j] = Fm[c];
       }
     };
     if (nx >= 8) {
@@ -107,6 +114,44 @@ __device__ __forceinline__ void xrows_body(const StageArgs<R>& a, long long row0
   }
   __syncthreads();
 
+  if (pair) {
+    // lane (q, h) = (x >> 1, x & 1): split h of the faces x' - 1/2, x' = 2q,
+    // 2q + 1, one field at a time; the two split values go into the field's
+    // own F+ and F- areas once every lane of the workgroup is past it
+    const int q = x >> 1, h = x & 1;
+    const R* b = h ? sFm + (P - 9 - 2 * q) : sFp + 2 * q;
+    R* dst = h ? sFm : sFp;
+    const int fa = 2 * q + h, fb = 2 * q + 1 - h;
+#pragma unroll
+    for (int c = 0; c < 5; ++c) {
+      R lo, hi;
+      if (act) {
+        const R* v = b + c * P;
+        weno7_pair<R, (S & 7)>(v[0], v[1], v[2], v[3], v[4], v[5], v[6], v[7], a.eps, lo, hi);
+      }
+      __syncthreads();
+      if (act) {
+        dst[c * P + fa] = lo;
+        dst[c * P + fb] = hi;
+      }
+    }
+    __syncthreads();
+    if (act) {
+      const int xr = (x + 1 == nx) ? 0 : x + 1;  // periodic: the right face of cell nx-1 is face -1/2
+#pragma unroll
+      for (int c = 0; c < 5; ++c) {
+        const R l = sFp[c * P + x] + sFm[c * P + x];
+        R* d = a.D + c * nc + rowbase + x;
+        if (x + 1 < nx || a.g.bc[0]) {
+          *d = (l - (sFp[c * P + xr] + sFm[c * P + xr])) * a.inv_d;
+        } else {
+          *d = l;  // finished by k_xbound
+        }
+      }
+    }
+    add_fixups(a.fixups, fix);
+    return;
+  }
   R Fh[5];
   if (act) {
     // face x - 1/2: F+ at x-4..x+2 (slots x..x+6), F- at x-3..x+3 (slots x+1..x+7)
@@ -148,7 +193,7 @@ __device__ __forceinline__ void xrows_body(const StageArgs<R>& a, long long row0
 template <class R, int S, int TB>
 __global__ void __launch_bounds__(TB) k_xface(StageArgs<R> a, int rpi) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  xrows_body<R, S>(a, (long long)blockIdx.x * rpi, rpi, reinterpret_cast<R*>(smem_raw));
+  xrows_body<R, S, true>(a, (long long)blockIdx.x * rpi, rpi, reinterpret_cast<R*>(smem_raw));
 }
 
 // Right boundary face of every row (outflow x): points nx-4..nx+3 (the last
@@ -344,9 +389,10 @@ __global__ void __launch_bounds__(256) k_march(StageArgs<R> a) {
 // y- or z-faces from an LDS tile (AX = 1 or 2).  A workgroup of 512 lanes
 // owns 16 cells along x (coalesced 128-byte rows) by 31 cells along AX at one
 // value of the remaining axis, so that its 32 face rows are exactly one face
-// per lane.  It stores the split AX-fluxes of its 16 x 39 points (4 ghost rows
-// on each side) in LDS, reconstructs the face rows and forms the divergence;
-// each lane's D is loaded before the reconstructions to hide its latency.
+// per lane (or, in pairs, one split of two faces per lane).  It stores the
+// split AX-fluxes of its 16 x 39 points (4 ghost rows on each side) in LDS,
+// reconstructs the face rows and forms the divergence; each lane's D is
+// loaded before the reconstructions to hide its latency.
 // LAST (z): adds D, does the RK combine with the cell's own stage input kept
 // in registers from the load, and writes the stage output.
 constexpr int kTileX = 16;
@@ -363,9 +409,15 @@ __device__ __forceinline__ void tile_limit(R H[5], const R* sFp, const R* sFm, i
       H, [&](int c, int k) { return ((k & 1) ? sFm : sFp)[(c * kP + f + 3 + (k >> 1)) * kPitch + col]; }, mu);
 }
 
-template <class R, int S, int AX, bool LAST, int kTileA>
+template <class R, int S, int AX, bool LAST, int kTileA, bool PAIRS>
 __device__ __forceinline__ void tile_body(const StageArgs<R>& a, int bx, int by, int bz, R* s) {
   constexpr int kTileP = kTileA + 8;  // points along AX
+  // Plain WENO faces are taken in pairs (see below); then the F- points are
+  // stored in reverse slot order, so that both splits read increasing slots.
+  // Not in the FP64 z tile: its stage input stays in registers for the
+  // combine, and a pair on top would cost a workgroup per CU.
+  constexpr bool kPair = PAIRS && (S & (kPP | kMusta)) == 0 && (!LAST || sizeof(R) == 4);
+  auto ms = [](int j) { return kPair ? kTileP - 1 - j : j; };
   R* sFp = s;                              // [5][kTileP][kTileXP]
   R* sFm = s + 5 * kTileP * kTileXP;       // [5][kTileP][kTileXP]
   const int nx = a.g.n[0], ny = a.g.n[1];
@@ -393,7 +445,7 @@ __device__ __forceinline__ void tile_body(const StageArgs<R>& a, int bx, int by,
 #pragma unroll
       for (int c = 0; c < 5; ++c) {
         sFp[(c * kTileP + ta + 4) * kTileXP + tx] = Fp[c];
-        sFm[(c * kTileP + ta + 4) * kTileXP + tx] = Fm[c];
+        sFm[(c * kTileP + ms(ta + 4)) * kTileXP + tx] = Fm[c];
       }
     }
   }
@@ -422,7 +474,7 @@ __device__ __forceinline__ void tile_body(const StageArgs<R>& a, int bx, int by,
 #pragma unroll
       for (int c = 0; c < 5; ++c) {
         sFp[(c * kTileP + j) * kTileXP + tx] = Fp[c];
-        sFm[(c * kTileP + j) * kTileXP + tx] = Fm[c];
+        sFm[(c * kTileP + ms(j)) * kTileXP + tx] = Fm[c];
       }
     }
   }
@@ -433,7 +485,49 @@ __device__ __forceinline__ void tile_body(const StageArgs<R>& a, int bx, int by,
   R Fh[5], Fh2[5];
   const bool has1 = xin && ta < nf;
   const bool has2 = (kTileA + 1) * kTileX > 512 && xin && threadIdx.x < kTileX && kTileA < nf;
-  if constexpr ((S & kMusta) != 0) {  // face row f: points in slots f..f+7
+  // Pairs: lane (q, h) = (ta >> 1, ta & 1) reconstructs split h (0: F+, 1: F-)
+  // of the face rows 2q and 2q + 1 from the 8 points they span, read in
+  // increasing slot order v0..v7: windows v0..v6 and v1..v7 share their
+  // differences and third-difference terms.  F+: v_j = slot 2q + j, the
+  // windows give rows 2q, 2q + 1; F- (mirrored stencils, reversed storage):
+  // v_j = F- at slot 2q + 8 - j, the windows give rows 2q + 1, 2q.  One field
+  // at a time: once every lane is past field c, its two split values per face
+  // row go into field c's own F+ and F- areas (rows in natural order), so a
+  // lane holds two results, not ten.
+  const int pq = ta >> 1, ph = ta & 1;
+  const bool hasp = kPair && xin && 2 * pq < nf;
+  if constexpr (kPair) {
+    const R* b = (ph ? sFm + (kTileP - 9 - 2 * pq) * kTileXP : sFp + 2 * pq * kTileXP) + tx;
+    R* dst = (ph ? sFm : sFp) + tx;
+    const int fa = 2 * pq + ph, fb = 2 * pq + 1 - ph;
+#pragma unroll
+    for (int c = 0; c < 5; ++c) {
+      R lo, hi, f2p, f2m;
+      if (hasp) {
+        const R* v = b + c * kTileP * kTileXP;
+        const R v0 = v[0], v1 = v[kTileXP], v2 = v[2 * kTileXP], v3 = v[3 * kTileXP], v4 = v[4 * kTileXP],
+                v5 = v[5 * kTileXP], v6 = v[6 * kTileXP], v7 = v[7 * kTileXP];
+        weno7_pair<R, (S & 7)>(v0, v1, v2, v3, v4, v5, v6, v7, a.eps, lo, hi);
+      }
+      if (has2) {  // row kTileA: F+ at slots kTileA..kTileA+6, F- at kTileA+7..kTileA+1 (reversed: 0..6)
+        const R* fp = sFp + (c * kTileP + kTileA) * kTileXP + tx;
+        const R* fm = sFm + c * kTileP * kTileXP + tx;
+        f2p = weno7<R, (S & 7)>(fp[0], fp[kTileXP], fp[2 * kTileXP], fp[3 * kTileXP], fp[4 * kTileXP],
+                                fp[5 * kTileXP], fp[6 * kTileXP], a.eps);
+        f2m = weno7<R, (S & 7)>(fm[0], fm[kTileXP], fm[2 * kTileXP], fm[3 * kTileXP], fm[4 * kTileXP],
+                                fm[5 * kTileXP], fm[6 * kTileXP], a.eps);
+      }
+      __syncthreads();
+      if (hasp) {
+        dst[(c * kTileP + fa) * kTileXP] = lo;
+        dst[(c * kTileP + fb) * kTileXP] = hi;
+      }
+      if (has2) {
+        sFp[(c * kTileP + kTileA) * kTileXP + tx] = f2p;
+        sFm[(c * kTileP + kTileA) * kTileXP + tx] = f2m;
+      }
+    }
+  } else if constexpr ((S & kMusta) != 0) {  // face row f: points in slots f..f+7
     auto at = [&](int f) {
       return [=](int c, int m) { return sFp[(c * kTileP + f + m) * kTileXP + tx]; };
     };
@@ -450,7 +544,7 @@ __device__ __forceinline__ void tile_body(const StageArgs<R>& a, int bx, int by,
                           fm[2 * kTileXP], fm[kTileXP], a.eps);
     }
   }
-  if ((S & kMusta) == 0 && has2) {
+  if ((S & kMusta) == 0 && !kPair && has2) {
 #pragma unroll
     for (int c = 0; c < 5; ++c) {
       const R* fp = sFp + (c * kTileP + kTileA) * kTileXP + tx;
@@ -466,21 +560,31 @@ __device__ __forceinline__ void tile_body(const StageArgs<R>& a, int bx, int by,
     if (has2) tile_limit<R, kTileP, kTileXP>(Fh2, sFp, sFm, kTileA, tx, a.pp_mu);
   }
   __syncthreads();
-  R* sF = s;  // [5][kTileA + 1][kTileXP]
-  if (has1) {
+  // face values: pairs keep the two splits apart in the F+ and F- areas
+  // ([5][kTileP][kTileXP], rows 0..kTileA) and form the face flux F+ + F-
+  // where it is used; otherwise sF [5][kTileA + 1][kTileXP] holds it
+  constexpr int kFP = kPair ? kTileP : kTileA + 1;
+  R* sF = s;
+  R* sG = sFm;
+  if (!kPair) {
+    if (has1) {
 #pragma unroll
-    for (int c = 0; c < 5; ++c) sF[(c * (kTileA + 1) + ta) * kTileXP + tx] = Fh[c];
-  }
-  if (has2) {
+      for (int c = 0; c < 5; ++c) sF[(c * kFP + ta) * kTileXP + tx] = Fh[c];
+    }
+    if (has2) {
 #pragma unroll
-    for (int c = 0; c < 5; ++c) sF[(c * (kTileA + 1) + kTileA) * kTileXP + tx] = Fh2[c];
+      for (int c = 0; c < 5; ++c) sF[(c * kFP + kTileA) * kTileXP + tx] = Fh2[c];
+    }
+    __syncthreads();
   }
-  __syncthreads();
 
   if (own_ok) {
 #pragma unroll
     for (int c = 0; c < 5; ++c) {
-      const R div = (sF[(c * (kTileA + 1) + ta) * kTileXP + tx] - sF[(c * (kTileA + 1) + ta + 1) * kTileXP + tx]) * a.inv_d;
+      const int i0 = (c * kFP + ta) * kTileXP + tx, i1 = i0 + kTileXP;
+      const R fl = kPair ? sF[i0] + sG[i0] : sF[i0];
+      const R fr = kPair ? sF[i1] + sG[i1] : sF[i1];
+      const R div = (fl - fr) * a.inv_d;
       R* d = a.D + c * nc + cell;
       if (!LAST) {
         *d = dpre[c] + div;
@@ -508,7 +612,7 @@ __device__ __forceinline__ void tile_body(const StageArgs<R>& a, int bx, int by,
 template <class R, int S, int AX, bool LAST, int A>
 __global__ void __launch_bounds__(512) k_tile(StageArgs<R> a) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  tile_body<R, S, AX, LAST, A>(a, blockIdx.x, blockIdx.y, blockIdx.z, reinterpret_cast<R*>(smem_raw));
+  tile_body<R, S, AX, LAST, A, true>(a, blockIdx.x, blockIdx.y, blockIdx.z, reinterpret_cast<R*>(smem_raw));
 }
 
 // ---------------------------------------------------------------------------
@@ -887,8 +991,8 @@ __global__ void __launch_bounds__(512) k_btile(BatchArgs<R> b) {
     } else {
       const int gx = (ev.g.n[0] + kTileX - 1) / kTileX, ga = (ev.g.n[AX] + A - 1) / A;
       const int bx = (int)(local % gx), by = (int)((local / gx) % ga), bz = (int)(local / ((long long)gx * ga));
-      if (A == 31) tile_body<R, S, AX, AX == 2, 31>(a, bx, by, bz, s);
-      else tile_body<R, S, AX, AX == 2, 32>(a, bx, by, bz, s);
+      if (A == 31) tile_body<R, S, AX, AX == 2, 31, false>(a, bx, by, bz, s);
+      else tile_body<R, S, AX, AX == 2, 32, false>(a, bx, by, bz, s);
     }
     __syncthreads();  // the next item overwrites the LDS tile
   }
@@ -904,7 +1008,7 @@ __global__ void __launch_bounds__(TB) k_bxrows(BatchArgs<R> b) {
     const BatchEvent& ev = b.ev[e];
     const int rpi = xrow_rows(ev.g.n[0], TB, (int)sizeof(R));
     const StageArgs<R> a = batch_stage_args<R>(ev, b.stage, b.eps, 0);
-    xrows_body<R, S>(a, (it - b.off[e]) * rpi, rpi, s);
+    xrows_body<R, S, false>(a, (it - b.off[e]) * rpi, rpi, s);
     __syncthreads();  // the next item overwrites the LDS rows
   }
 }
