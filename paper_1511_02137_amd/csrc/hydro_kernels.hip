@@ -57,6 +57,25 @@ __device__ __forceinline__ void point_values(const R u[5], R Fp[5], R Fm[5], uns
   }
 }
 
+// SSP-RK3 combine of the last face kernel of a stage (z).  With L = Dxy + Dz
+// (Dxy: the x and y divergences and the source, already in D; Dz: the z
+// divergence), the stage value w + dt L enters as p = w + dt Dxy, then
+// p + dt Dz (two fmas), so that a kernel can fold w into p before its
+// reconstructions and keep one value per field instead of two.  Stage 0
+// returns L itself.
+template <class R>
+__device__ __forceinline__ R rk_pre(int stage, R w, R dxy, R dt) {
+  return stage == 0 ? dxy : fma(dt, dxy, w);
+}
+template <class R>
+__device__ __forceinline__ R rk_out(int stage, R p, R dz, R dt, const R* Un, long long i) {
+  if (stage == 0) return p + dz;
+  const R v = fma(dt, dz, p);
+  if (stage == 1) return v;
+  if (stage == 2) return R(0.75) * Un[i] + R(0.25) * v;
+  return R(1.0 / 3.0) * Un[i] + R(2.0 / 3.0) * v;
+}
+
 template <class R, int S, bool PAIRS>
 __device__ __forceinline__ void xrows_body(const StageArgs<R>& a, long long row0, int rpi, R* s) {
   const int nx = a.g.n[0];
@@ -366,19 +385,8 @@ __global__ void __launch_bounds__(256) k_march(StageArgs<R> a) {
       if (!LAST) {
         *d = *d + div;
       } else {
-        const R L = *d + div;
-        const R w = a.W[c * nc + cell];
-        R outv;
-        if (a.stage == 0) {
-          outv = L;  // right-hand side only
-        } else if (a.stage == 1) {
-          outv = w + a.dt * L;
-        } else if (a.stage == 2) {
-          outv = R(0.75) * a.Un[c * nc + cell] + R(0.25) * (w + a.dt * L);
-        } else {
-          outv = R(1.0 / 3.0) * a.Un[c * nc + cell] + R(2.0 / 3.0) * (w + a.dt * L);
-        }
-        a.out[c * nc + cell] = outv;
+        const R p = rk_pre(a.stage, a.W[c * nc + cell], *d, a.dt);
+        a.out[c * nc + cell] = rk_out(a.stage, p, div, a.dt, a.Un, c * nc + cell);
       }
     }
   }
@@ -393,8 +401,8 @@ __global__ void __launch_bounds__(256) k_march(StageArgs<R> a) {
 // split AX-fluxes of its 16 x 39 points (4 ghost rows on each side) in LDS,
 // reconstructs the face rows and forms the divergence; each lane's D is
 // loaded before the reconstructions to hide its latency.
-// LAST (z): adds D, does the RK combine with the cell's own stage input kept
-// in registers from the load, and writes the stage output.
+// LAST (z): adds D, does the RK combine (rk_pre, rk_out) and writes the
+// stage output.
 constexpr int kTileX = 16;
 constexpr int kTileXP = kTileX;      // x pitch of the LDS arrays (128-byte rows)
 
@@ -414,9 +422,7 @@ __device__ __forceinline__ void tile_body(const StageArgs<R>& a, int bx, int by,
   constexpr int kTileP = kTileA + 8;  // points along AX
   // Plain WENO faces are taken in pairs (see below); then the F- points are
   // stored in reverse slot order, so that both splits read increasing slots.
-  // Not in the FP64 z tile: its stage input stays in registers for the
-  // combine, and a pair on top would cost a workgroup per CU.
-  constexpr bool kPair = PAIRS && (S & (kPP | kMusta)) == 0 && (!LAST || sizeof(R) == 4);
+  constexpr bool kPair = PAIRS && (S & (kPP | kMusta)) == 0;
   auto ms = [](int j) { return kPair ? kTileP - 1 - j : j; };
   R* sFp = s;                              // [5][kTileP][kTileXP]
   R* sFm = s + 5 * kTileP * kTileXP;       // [5][kTileP][kTileXP]
@@ -434,12 +440,24 @@ __device__ __forceinline__ void tile_body(const StageArgs<R>& a, int bx, int by,
   const bool xin = x < nx;
   unsigned fix = 0;
 
-  R own[5];
+  const int ac = a0 + ta;
+  const bool own_ok = xin && ta < kTileA && ac < n;
+  const long long cell = base + (long long)ac * stride;
+  // dpre: the own cell's D, loaded early so that its latency overlaps the
+  // ghost rows and the reconstructions; LAST: loaded with the cell's W and
+  // folded into the combine's p = w + dt D at once (rk_pre), so W need not
+  // stay in registers
+  R dpre[5];
   // pass 1: own cell (slot ta + 4)
   {
     const int p = a0 + ta;
     if (xin && ta < kTileA) {
+      R own[5];
       load5(a.W, nc, base + (long long)map_idx(p, n, bc) * stride, own);
+      if (LAST && own_ok) {
+#pragma unroll
+        for (int c = 0; c < 5; ++c) dpre[c] = a.D[c * nc + cell];
+      }
       R Fp[5], Fm[5];
       point_values<R, S, AX>(own, Fp, Fm, fix);
 #pragma unroll
@@ -447,19 +465,15 @@ __device__ __forceinline__ void tile_body(const StageArgs<R>& a, int bx, int by,
         sFp[(c * kTileP + ta + 4) * kTileXP + tx] = Fp[c];
         sFm[(c * kTileP + ms(ta + 4)) * kTileXP + tx] = Fm[c];
       }
+      if (LAST && own_ok) {
+#pragma unroll
+        for (int c = 0; c < 5; ++c) dpre[c] = rk_pre(a.stage, own[c], dpre[c], a.dt);
+      }
     }
   }
-  // the own cell's D, loaded early so that its latency overlaps the ghost
-  // rows and the reconstructions
-  const int ac = a0 + ta;
-  const bool own_ok = xin && ta < kTileA && ac < n;
-  const long long cell = base + (long long)ac * stride;
-  R dpre[5];
-  if (own_ok) {
+  if (!LAST && own_ok) {
 #pragma unroll
-    for (int c = 0; c < 5; ++c) {
-      dpre[c] = a.D[c * nc + cell];
-    }
+    for (int c = 0; c < 5; ++c) dpre[c] = a.D[c * nc + cell];
   }
   // pass 2: 4 ghost rows on each side (128 lanes)
   if (threadIdx.x < 8 * kTileX) {
@@ -585,23 +599,10 @@ __device__ __forceinline__ void tile_body(const StageArgs<R>& a, int bx, int by,
       const R fl = kPair ? sF[i0] + sG[i0] : sF[i0];
       const R fr = kPair ? sF[i1] + sG[i1] : sF[i1];
       const R div = (fl - fr) * a.inv_d;
-      R* d = a.D + c * nc + cell;
       if (!LAST) {
-        *d = dpre[c] + div;
+        a.D[c * nc + cell] = dpre[c] + div;
       } else {
-        const R L = dpre[c] + div;
-        const R w = own[c];
-        R outv;
-        if (a.stage == 0) {
-          outv = L;
-        } else if (a.stage == 1) {
-          outv = w + a.dt * L;
-        } else if (a.stage == 2) {
-          outv = R(0.75) * a.Un[c * nc + cell] + R(0.25) * (w + a.dt * L);
-        } else {
-          outv = R(1.0 / 3.0) * a.Un[c * nc + cell] + R(2.0 / 3.0) * (w + a.dt * L);
-        }
-        a.out[c * nc + cell] = outv;
+        a.out[c * nc + cell] = rk_out(a.stage, dpre[c], div, a.dt, a.Un, c * nc + cell);
       }
     }
   }

@@ -161,8 +161,11 @@ def test_batch_rejects_incompatible_events():
 
 
 @pytest.mark.parametrize("precision", ["f64", "f32"])
-def test_single_event_x_tile_matches_row_kernel(precision):
-    w = W.small_event(n=(37, 21, 18))
+@pytest.mark.parametrize("n", [(37, 21, 18), (36, 21, 18)])
+def test_single_event_x_tile_matches_row_kernel(precision, n):
+    """x tiles against x rows, bit for bit; rows of even length take their
+    faces in pairs, odd rows one face per lane."""
+    w = W.small_event(n=n)
     w.jets[0].x0 = (-0.5, 0.1, 0.05)
     outs = []
     for xk in (0, 1):
