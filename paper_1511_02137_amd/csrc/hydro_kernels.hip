@@ -422,7 +422,9 @@ __device__ __forceinline__ void tile_body(const StageArgs<R>& a, int bx, int by,
   constexpr int kTileP = kTileA + 8;  // points along AX
   // Plain WENO faces are taken in pairs (see below); then the F- points are
   // stored in reverse slot order, so that both splits read increasing slots.
-  constexpr bool kPair = PAIRS && (S & (kPP | kMusta)) == 0;
+  // FP64 32-cell y tiles keep one face per lane: their 33rd face row on top
+  // of a pair takes them to 84 VGPRs, one workgroup per CU fewer (slower).
+  constexpr bool kPair = PAIRS && (S & (kPP | kMusta)) == 0 && (sizeof(R) == 4 || kTileA == 31 || LAST);
   auto ms = [](int j) { return kPair ? kTileP - 1 - j : j; };
   R* sFp = s;                              // [5][kTileP][kTileXP]
   R* sFm = s + 5 * kTileP * kTileXP;       // [5][kTileP][kTileXP]

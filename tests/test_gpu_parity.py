@@ -86,8 +86,11 @@ def test_small_event_fp64_matches_oracle():
 
 @pytest.mark.parametrize("n,bc", [((37, 29, 23), "outflow"), ((37, 29, 23), "periodic"), ((8, 8, 8), "outflow"),
                                   ((65, 3, 70), "outflow"), ((300, 9, 5), "periodic"), ((1, 1, 40), "outflow"),
-                                  ((257, 6, 7), "outflow")])
+                                  ((257, 6, 7), "outflow"), ((20, 32, 64), "outflow"), ((22, 64, 32), "periodic")])
 def test_ragged_grids_fp64(n, bc):
+    """FP64 parity on ragged and small grids: odd and even x rows (one face
+    per lane, face pairs), 31- and 32-cell y/z tiles (the latter with their
+    33rd face row), periodic and outflow boundaries."""
     w = W.small_event(3, n=n, steps=3)
     w.jets[0].x0 = (-0.3 * n[0] * 0.1 / 2 if n[0] > 4 else 0.0, 0.0123, -0.0071)
     pb, st = run_oracle(w, 3, bc=(bc,) * 3)
