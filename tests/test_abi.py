@@ -124,3 +124,14 @@ def test_product_fails_loudly_without_library_or_gpu(tmp_path):
             "    except RuntimeError as e:\n        print('raised', e)\n")
     r = subprocess.run([sys.executable, "-c", code], cwd=root, capture_output=True, text=True, timeout=300)
     assert "gpu present" in r.stdout or "raised libhydro needs a GPU" in r.stdout, r.stdout + r.stderr
+
+
+@pytest.mark.parametrize("argv,env", [(["--gpus", "2"], {}), ([], {"WORLD_SIZE": "2"})])
+def test_bench_refuses_more_than_one_gpu(argv, env):
+    """bench.py measures one GPU: asked for more (flag or a launcher's
+    WORLD_SIZE) it exits with status 2 and says so, before touching a GPU."""
+    e = dict(os.environ, **env)
+    r = subprocess.run(["python3", os.path.join(ROOT, "bench.py")] + argv, capture_output=True, text=True,
+                       env=e, timeout=120)
+    assert r.returncode == 2
+    assert "measures one GPU" in r.stderr and r.stdout == ""
