@@ -271,3 +271,39 @@ def test_eps2_closed_form_uniform_field(n):
     sy = 0.01 * ny * (ny * ny - 1) / 12
     ref = (sy * nx - sx * ny) / (sy * nx + sx * ny)
     assert O.eps2(pb, U) == pytest.approx(ref, abs=1e-14)
+
+
+@pytest.mark.parametrize("n", [(8, 8, 8), (10, 6, 7), (6, 12, 9), (7, 9, 4)])
+def test_eps2_closed_form_picks_the_z0_planes(n):
+    """A uniform background at rest plus one hot cell on each of the planes
+    next to z = 0.  The z = 0 value is the mean of the two middle planes
+    (even nz: planes nz/2 - 1 and nz/2, at z = -+dz/2) or the middle plane
+    (odd nz): a spike on those planes enters with weight 1/2 (even) or 1
+    (odd), a spike on any other plane not at all.  With sum_i x_i^2 =
+    dx^2 n (n^2 - 1)/12 for centred cells the background sums are closed
+    forms, so eps2 is known exactly; choosing other planes, a wrong weight or
+    a shifted origin changes it."""
+    nx, ny, nz = n
+    bg, s = 0.5, 40.0
+    prim = W.uniform_prim(n, e=bg, v=(0, 0, 0))
+    # spikes: (i, j, plane)
+    if nz % 2 == 0:
+        planes, wt = (nz // 2 - 1, nz // 2), 0.5
+    else:
+        planes, wt = ((nz - 1) // 2,), 1.0
+    cells = [(1, ny - 2, planes[0]), (nx - 1, 2, planes[-1])]
+    off = [(nx // 2, 0, planes[-1] + 1), (0, ny // 2, planes[0] - 1)]  # neighbouring planes: no weight
+    for i, j, k in cells + off:
+        prim[0, k, j, i] += s
+    pb = O.Problem(n=n)
+    U = O.prim_to_cons(pb, prim)
+    dx = 0.1
+    xc = lambda i, m: (i - 0.5 * (m - 1)) * dx
+    sx = dx * dx * nx * (nx * nx - 1) / 12
+    sy = dx * dx * ny * (ny * ny - 1) / 12
+    num = bg * (sy * nx - sx * ny)
+    den = bg * (sy * nx + sx * ny)
+    for i, j, _ in cells:
+        num += wt * s * (xc(j, ny) ** 2 - xc(i, nx) ** 2)
+        den += wt * s * (xc(j, ny) ** 2 + xc(i, nx) ** 2)
+    assert O.eps2(pb, U) == pytest.approx(num / den, rel=1e-13, abs=1e-14)
