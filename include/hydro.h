@@ -113,7 +113,10 @@ typedef struct {
   int32_t precision;   /* hydro_precision */
   int32_t weno;        /* hydro_weno (default HYDRO_WENO_Z) */
   int32_t deposit;     /* hydro_deposit */
-  double weno_eps;     /* epsilon of the weights, (GeV/fm^3)^2 scale; 1e-6 */
+  double weno_eps;     /* epsilon of the weights, (GeV/fm^3)^2 scale; 1e-6.
+                          At least 1e-30 in FP64 and 1e-12 in FP32 (the
+                          weights' products and squares stay in range);
+                          smaller values return HYDRO_EINVAL */
   int32_t weno_p;      /* exponent of the WENO-Z weights; 2 (only 2 is built) */
   int32_t strict;      /* 1: hydro_sums reports HYDRO_ENONPHYS after fix-ups */
   double eos_dof;      /* g of e = g pi^2/30 T^4/(hbar c)^3; 47.5 */

@@ -68,10 +68,16 @@ class Eps2Problem:
         eps = self.h.loss_eps2()
         return eps, cks, self.h.U.clone(), prim
 
-    def backward(self, cks: List[Checkpoint], U_final, prim, scale: float = 1.0):
+    def backward(self, cks: List[Checkpoint], U_final, prim, scale: float = 1.0, params=None):
         """scale * (d eps2/d e_init [device (nz, ny, nx)], d eps2/d jet params
-        [device (njet, 5): kappa_rad, kappa_coll, x0, y0, z0])."""
+        [device (njet, 5): kappa_rad, kappa_coll, x0, y0, z0]).  The reverse
+        sweep recomputes the stage states with the context's current jet;
+        params = (kappa_rad, kappa_coll, x0, y0) of the forward being
+        differentiated re-applies them first (needed whenever another forward
+        ran in between)."""
         import torch
+        if params is not None:
+            self.set_params(*params)
         lam = torch.empty_like(U_final)
         self.h.loss_eps2(U_final, seed=lam, scale=scale)
         grad = torch.zeros((max(1, self.h.njet), 5), dtype=torch.float64, device=U_final.device)
@@ -96,16 +102,19 @@ def _function():
 
         @staticmethod
         def forward(ctx, e_init, kappa_rad, kappa_coll, jet_xy, problem):
-            eps, cks, U_final, prim = problem.forward(e_init, float(kappa_rad), float(kappa_coll),
-                                                      float(jet_xy[0]), float(jet_xy[1]))
+            params = (float(kappa_rad), float(kappa_coll), float(jet_xy[0]), float(jet_xy[1]))
+            eps, cks, U_final, prim = problem.forward(e_init, *params)
             ctx.problem, ctx.cks, ctx.U_final, ctx.prim = problem, cks, U_final, prim
+            # the problem's context is shared: another forward may set other
+            # jet parameters before this backward runs
+            ctx.params = params
             ctx.dtypes = (e_init.dtype, kappa_rad.dtype, kappa_coll.dtype, jet_xy.dtype)
             ctx.devices = (e_init.device, kappa_rad.device, kappa_coll.device, jet_xy.device)
             return eps
 
         @staticmethod
         def backward(ctx, g):
-            gde, grad = ctx.problem.backward(ctx.cks, ctx.U_final, ctx.prim, scale=float(g))
+            gde, grad = ctx.problem.backward(ctx.cks, ctx.U_final, ctx.prim, scale=float(g), params=ctx.params)
             dt, dv = ctx.dtypes, ctx.devices
             return (gde.to(device=dv[0], dtype=dt[0]), grad[0, 0].to(device=dv[1], dtype=dt[1]),
                     grad[0, 1].to(device=dv[2], dtype=dt[2]), grad[0, 2:4].to(device=dv[3], dtype=dt[3]), None)

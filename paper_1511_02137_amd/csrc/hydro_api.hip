@@ -267,6 +267,11 @@ int adjoint_impl(hydro_ctx* ctx, const R* Uc, int64_t step0, const double* E0, i
   // keep the context's jet energies and ledger
   HYDRO_TRY(launch_copy_f64(ctx->dev->E_jet, ctx->Esave, kMaxJets, st));
   HYDRO_TRY(launch_copy_f64(&ctx->dev->ledger, ctx->Esave + kMaxJets, 1, st));
+  // and its fix-up count: the recomputed stages and the reverse kernels
+  // recover primitives again, which must not count as new fix-ups of the run
+  // (an 8-byte move, bit for bit)
+  HYDRO_TRY(launch_copy_f64(reinterpret_cast<const double*>(&ctx->dev->fixups),
+                            reinterpret_cast<double*>(&ctx->dev->fixups_save), 1, st));
   // the checkpoint's jet energies (host memory): ordered after the saves above
   HYDRO_TRY(hipStreamSynchronize(st));
   if (ctx->njet > 0) HYDRO_TRY(hipMemcpy(ctx->dev->E_jet, E0, (size_t)ctx->njet * sizeof(double), hipMemcpyHostToDevice));
@@ -331,6 +336,8 @@ int adjoint_impl(hydro_ctx* ctx, const R* Uc, int64_t step0, const double* E0, i
   }
   HYDRO_TRY(launch_copy_f64(ctx->Esave, ctx->dev->E_jet, kMaxJets, st));
   HYDRO_TRY(launch_copy_f64(ctx->Esave + kMaxJets, &ctx->dev->ledger, 1, st));
+  HYDRO_TRY(launch_copy_f64(reinterpret_cast<const double*>(&ctx->dev->fixups_save),
+                            reinterpret_cast<double*>(&ctx->dev->fixups), 1, st));
 #undef HYDRO_TRY
   return HYDRO_OK;
 }

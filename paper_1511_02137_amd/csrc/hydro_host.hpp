@@ -46,7 +46,12 @@ inline bool config_ok(const hydro_config* c, std::string* why) {
     if (c->limiter != HYDRO_LIMITER_NONE) return fail("MUSTA-FORCE is built without the limiter");
   }
   if (c->deposit != HYDRO_DEP_NGP && c->deposit != HYDRO_DEP_GAUSS) return fail("bad deposit");
-  if (!(c->weno_eps > 0.0)) return fail("weno_eps must be > 0");
+  if (!(c->weno_eps > 0.0) || !std::isfinite(c->weno_eps)) return fail("weno_eps must be > 0");
+  // FP64 weights take products of four squared indicators (each >= eps), which
+  // stay normal for eps >= 1e-30; FP32 weights square tau / b_k (b_k >= eps),
+  // which stays below the FP32 maximum for tau up to 1e7 when eps >= 1e-12
+  if (c->weno_eps < (c->precision == HYDRO_F32 ? 1e-12 : 1e-30))
+    return fail("weno_eps too small for the weights' arithmetic (FP64 needs >= 1e-30, FP32 >= 1e-12)");
   if (c->weno_p != 2) return fail("only weno_p = 2 is built");
   if (!(c->eos_dof > 0.0) || !(c->hbarc > 0.0)) return fail("eos_dof and hbarc must be > 0");
   return true;

@@ -46,6 +46,7 @@ struct DevScalars {
   double ledger;              // deposited energy so far
   double sums[5];             // last conservation sums (x dV)
   unsigned long long fixups;  // conserved->primitive fix-ups
+  unsigned long long fixups_save;  // fixups on entry to an adjoint sweep (restored on exit)
 };
 
 // Arguments of the stage kernels (device pointers).

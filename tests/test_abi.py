@@ -78,10 +78,14 @@ def test_workspace_bytes(lib):
 
 
 @pytest.mark.parametrize("field,value", [("dt", 0.0), ("weno", 7), ("deposit", 3), ("weno_p", 3),
-                                         ("precision", 5), ("weno_eps", 0.0)])
+                                         ("precision", 5), ("weno_eps", 0.0), ("weno_eps", 1e-40),
+                                         ("weno_eps", float("inf")), ("f32_weno_eps", 1e-13)])
 def test_init_rejects_bad_config_without_side_effects(lib, field, value):
-    c = H.make_config((16, 16, 16))
-    setattr(c, field, value)
+    # weno_eps below 1e-30 (FP64) or 1e-12 (FP32): the weights' common
+    # denominator (a product of four squared indicators) would leave the
+    # normal range, or tau / b squared would overflow FP32
+    c = H.make_config((16, 16, 16), precision="f32" if field.startswith("f32_") else "f64")
+    setattr(c, field.replace("f32_", ""), value)
     h = ctypes.c_void_p(123)
     rc = lib.hydro_init(ctypes.byref(c), None, ctypes.c_void_p(1), ctypes.c_void_p(256), 1 << 30, None,
                         ctypes.byref(h))

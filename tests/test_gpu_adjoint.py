@@ -367,3 +367,58 @@ def test_torch_gradcheck_small():
                                   atol=1e-9, rtol=1e-4, fast_mode=True)
     assert ok
     pb.h.close()
+
+
+def test_backward_after_another_forward_uses_its_own_parameters():
+    """Two differentiable forwards at different jet parameters on one problem,
+    then the backward of the first: it must re-apply the first forward's
+    kappas and origin before recomputing its stage states, so its gradients
+    equal those of a lone forward + backward at those parameters (bitwise:
+    the same kernels on the same inputs)."""
+    A = adjoint_mod()
+    w = small(n=(16, 16, 16), steps=3)
+    pb = A.Eps2Problem(w, ckpt_every=2)
+    j = w.jets[0]
+    e0 = torch.tensor(w.prim0[0], dtype=torch.float64, device="cuda", requires_grad=True)
+
+    def leaf(v):
+        return torch.tensor(v, dtype=torch.float64, requires_grad=True)
+
+    pa = (leaf(j.kappa_rad), leaf(j.kappa_coll), leaf(list(j.x0[:2])))
+    pbb = (leaf(2.0 * j.kappa_rad), leaf(0.5 * j.kappa_coll), leaf([j.x0[0] + 0.07, j.x0[1] - 0.05]))
+    ea = A.eps2(e0, *pa, pb)
+    eb = A.eps2(e0, *pbb, pb)
+    assert float(ea) != float(eb)
+    ga = torch.autograd.grad(ea, [e0, *pa])
+    # the lone run at the first parameters
+    e1 = torch.tensor(w.prim0[0], dtype=torch.float64, device="cuda", requires_grad=True)
+    p1 = (leaf(j.kappa_rad), leaf(j.kappa_coll), leaf(list(j.x0[:2])))
+    e_alone = A.eps2(e1, *p1, pb)
+    g1 = torch.autograd.grad(e_alone, [e1, *p1])
+    assert float(e_alone) == float(ea)
+    for a, b in zip(ga, g1):
+        assert torch.equal(a.cpu(), b.cpu())
+    pb.h.close()
+
+
+def test_adjoint_sweep_leaves_the_fixup_count_alone():
+    """The reverse sweep recomputes the segment's stages and recovers
+    primitives in its own kernels; none of that may add to the run's fix-up
+    count (hydro_diag), here with a non-admissible cell in the checkpoint so
+    that the recomputation does go through the fix-up branch."""
+    from paper_1511_02137_amd import hydro as H
+    w = small(n=(16, 16, 16), steps=2)
+    h = H.from_workload(w, adjoint_k=2)
+    h.U[0, 8, 8, 8] = -1.0
+    U0 = h.U.clone()
+    _, step0, E0 = h.get_state()
+    h.step(2)
+    f = h.fixups()
+    assert f > 0
+    lam = torch.empty_like(h.U)
+    h.loss_eps2(h.U, seed=lam)
+    grad = torch.zeros((1, 5), dtype=torch.float64, device="cuda")
+    h.adjoint_step(U0, step0, E0, 2, lam, grad)
+    torch.cuda.synchronize()
+    assert h.fixups() == f
+    h.close()

@@ -411,3 +411,30 @@ def test_kernel_variants_are_bitwise_identical(precision):
         outs.append(h.U.clone())
     for u in outs[1:]:
         assert torch.equal(outs[0], u)
+
+
+@pytest.mark.parametrize("precision,eps", [("f64", 1e-30), ("f32", 1e-12)])
+def test_smallest_accepted_weno_eps_on_flat_plus_step(precision, eps):
+    """The smallest weno_eps the library accepts (FP64 1e-30, FP32 1e-12) on a
+    field that is flat on both sides of a step (a Riemann problem e = 10 | 1
+    along x): the common-denominator FP64 weights and the FP32 squares stay
+    finite, and the run matches the oracle's per-stencil weights (FP64 1e-12
+    relative L-infinity, FP32 relative L2 of e and |v| 1e-5 after 5 steps)."""
+    w = W.vacuum_riemann(N=64, e_right=1.0, axis=0)
+    steps = 5
+    pb = oracle_problem(w, weno_eps=eps)
+    st = O.run(pb, O.prim_to_cons(pb, w.prim0), steps, [])
+    cfg = H().make_config(w.n, w.dx, w.dt, w.t0, w.bc, precision=precision, weno_eps=eps)
+    h = H().Hydro(cfg, w.prim0)
+    h.step(steps)
+    Ug = h.U.double().cpu().numpy()
+    assert np.isfinite(Ug).all()
+    if precision == "f64":
+        err = rel_linf(Ug, st.U)
+        report("flat + step, eps %g" % eps, err)
+        assert np.all(err <= 1e-12), err
+    else:
+        e_err, v_err = fp32_errors(Ug, st.U, pb)
+        print("flat + step FP32, eps %g: rel L2 e %.2e |v| %.2e" % (eps, e_err, v_err), flush=True)
+        assert e_err <= 1e-5 and v_err <= 1e-5
+    h.close()
