@@ -198,6 +198,22 @@ int hydro_primitives(hydro_ctx* ctx, const void* U, void* prim, void* stream);
  * Returns HYDRO_ENONPHYS in strict mode after a fix-up. */
 int hydro_sums(hydro_ctx* ctx, const void* U, double out[6], void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the sums
+ * of hydro_sums, asynchronous on `stream` and without any allocation.
+ *   out  device FP64 [6], written: out[0..4] = sum of E, Mx, My, Mz, N times
+ *        dV, out[5] = deposited-energy ledger; the context's last sums are
+ *        updated as by hydro_sums.  Host memory returns HYDRO_EINVAL.
+ * The same kernels and fixed reduction order as hydro_sums, so the values
+ * are bit for bit those of hydro_sums.  The reduction partials live in a
+ * static device array of the library (kSumBlocks x 5 FP64 = 40 KiB per
+ * device, held until the process ends) instead of the workspace; every call
+ * overwrites all of them, so any grid that hydro_init accepts fits and no
+ * size is refused.  Calls that overlap on one device (other streams, other
+ * contexts) share that array and race: serialise them.  Strict mode is not
+ * checked here (no synchronisation); hydro_diag reports fix-ups. */
+int hydro_sums_noalloc(hydro_ctx* ctx, const void* U, double* out, void* stream);
+
 /* Synchronous: time, step index and the jets' remaining energies. */
 int hydro_get_state(hydro_ctx* ctx, double* t, int64_t* step, double* E_jet, int n_jet);
 int hydro_set_state(hydro_ctx* ctx, int64_t step, const double* E_jet, int n_jet, double ledger);

@@ -10,6 +10,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -24,6 +25,7 @@ using namespace hydro;
 struct hydro_ctx {
   hydro_config cfg;
   Grid g;
+  int device = 0;    // HIP device current at hydro_init
   int njet = 0;
   hydro_jet jets[kMaxJets];
   DevScalars* dev = nullptr;
@@ -64,6 +66,50 @@ struct hydro_ctx {
 namespace {
 
 thread_local std::string g_init_error;
+
+// Reduction partials of hydro_sums_noalloc: the kSumBlocks x 5 FP64 partial
+// sums (40 KiB) of the conservation-sum reduction, one copy per device, held
+// until the process ends.  The reduction always runs kSumBlocks blocks and
+// each block overwrites its own five partials, so the array needs no
+// clearing and any grid fits.  Host code never passes the symbol itself: the
+// per-device address comes from hipGetSymbolAddress, taken once per device in
+// hydro_init with that device current.
+constexpr int kMaxDevices = 64;
+constexpr int kScratchDoubles = kSumBlocks * 5;
+
+}  // namespace
+
+static __device__ __align__(256) double scratch[kScratchDoubles];
+
+namespace {
+
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[kMaxDevices] = {};
+hipError_t g_scratch_err[kMaxDevices] = {};
+
+// Takes the address of `scratch` on device `dev` (current) once.
+void scratch_setup(int dev) {
+  if (dev < 0 || dev >= kMaxDevices) return;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch_ptr[dev]) return;
+  double* ptr = nullptr;
+  hipError_t e = hipGetSymbolAddress(reinterpret_cast<void**>(&ptr), HIP_SYMBOL(scratch));
+  if (e == hipSuccess && ptr) {
+    g_scratch_ptr[dev] = ptr;
+  } else {
+    g_scratch_err[dev] = e == hipSuccess ? hipErrorInvalidSymbol : e;
+  }
+}
+
+double* scratch_for(int dev, hipError_t* why) {
+  if (dev < 0 || dev >= kMaxDevices) {
+    *why = hipErrorInvalidDevice;
+    return nullptr;
+  }
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  *why = g_scratch_err[dev];
+  return g_scratch_ptr[dev];
+}
 
 struct WsLayout {
   size_t U1, U2, D, part, eps_part, eps_out, fwd_total;
@@ -435,7 +481,14 @@ int hydro_init(const hydro_config* cfg, const double* prim0, void* U, void* work
   ctx->seg = 32;
   hipStream_t st = static_cast<hipStream_t>(stream);
 
-  hipError_t e = hipMalloc(&ctx->dev, sizeof(DevScalars));
+  hipError_t e = hipGetDevice(&ctx->device);
+  if (e != hipSuccess) {
+    g_init_error = std::string("hipGetDevice: ") + hipGetErrorString(e);
+    delete ctx;
+    return HYDRO_EDEVICE;
+  }
+  scratch_setup(ctx->device);
+  e = hipMalloc(&ctx->dev, sizeof(DevScalars));
   if (e != hipSuccess) {
     g_init_error = std::string("hipMalloc: ") + hipGetErrorString(e);
     delete ctx;
@@ -563,6 +616,24 @@ int hydro_sums(hydro_ctx* ctx, const void* U, double out[6], void* stream) {
   for (int c = 0; c < 5; ++c) out[c] = h.sums[c];
   out[5] = h.ledger;
   if (ctx->cfg.strict && h.fixups > 0) return fail(ctx, HYDRO_ENONPHYS, "non-admissible cells were fixed up");
+  return HYDRO_OK;
+}
+
+int hydro_sums_noalloc(hydro_ctx* ctx, const void* U, double* out, void* stream) {
+  if (!ctx || !U || !out) return fail(ctx, HYDRO_EINVAL, "bad arguments to hydro_sums_noalloc");
+  if (!is_device_pointer(out)) return fail(ctx, HYDRO_EINVAL, "hydro_sums_noalloc: out must be device memory");
+  static_assert(kScratchDoubles >= kSumBlocks * 5, "scratch holds the reduction partials");
+  hipError_t why = hipSuccess;
+  double* part = scratch_for(ctx->device, &why);
+  if (!part) return hip_fail(ctx, why, "hydro_sums_noalloc: address of the static scratch array");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const double dV = ctx->cfg.dx[0] * ctx->cfg.dx[1] * ctx->cfg.dx[2];
+  hipError_t e = ctx->cfg.precision == HYDRO_F32
+                     ? launch_sums<float>(static_cast<const float*>(U), ctx->g.nc, dV, part, ctx->dev, st)
+                     : launch_sums<double>(static_cast<const double*>(U), ctx->g.nc, dV, part, ctx->dev, st);
+  if (e == hipSuccess) e = launch_copy_f64(ctx->dev->sums, out, 5, st);
+  if (e == hipSuccess) e = launch_copy_f64(&ctx->dev->ledger, out + 5, 1, st);
+  if (e != hipSuccess) return hip_fail(ctx, e, "hydro_sums_noalloc launch");
   return HYDRO_OK;
 }
 

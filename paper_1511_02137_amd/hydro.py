@@ -31,7 +31,7 @@ EXPORTED = [
     "hydro_init_vjp", "hydro_batch_workspace_bytes", "hydro_batch_create", "hydro_batch_add_jet", "hydro_batch_run",
     "hydro_batch_rhs", "hydro_batch_set_option", "hydro_batch_get_option", "hydro_batch_autotune",
     "hydro_batch_sums", "hydro_batch_get_state", "hydro_batch_diag", "hydro_batch_last_error",
-    "hydro_batch_destroy",
+    "hydro_batch_destroy", "hydro_sums_noalloc",
 ]
 OPT_YZ_KERNEL, OPT_MARCH_SEG, OPT_X_KERNEL, OPT_ADJ_SKIP_N = 0, 1, 2, 3
 BOPT_BLOCKS_X, BOPT_BLOCKS_Y, BOPT_BLOCKS_Z, BOPT_GRAPH, BOPT_X_ROWS = 0, 1, 2, 3, 4
@@ -99,6 +99,7 @@ def load_library(path: str = LIB_PATH):
     lib.hydro_primitives.argtypes = [vp, vp, vp, vp]
     lib.hydro_rhs.argtypes = [vp, vp, ctypes.c_double, vp, vp]
     lib.hydro_sums.argtypes = [vp, vp, dp, vp]
+    lib.hydro_sums_noalloc.argtypes = [vp, vp, vp, vp]
     lib.hydro_get_state.argtypes = [vp, dp, ctypes.POINTER(ctypes.c_int64), dp, ctypes.c_int]
     lib.hydro_set_state.argtypes = [vp, ctypes.c_int64, dp, ctypes.c_int, ctypes.c_double]
     lib.hydro_diag.argtypes = [vp, ctypes.POINTER(ctypes.c_int64)]
@@ -139,7 +140,7 @@ def load_library(path: str = LIB_PATH):
     for name in ("hydro_init", "hydro_add_jet", "hydro_rk3_step", "hydro_primitives", "hydro_rhs", "hydro_sums",
                  "hydro_get_state", "hydro_set_state", "hydro_diag", "hydro_profile", "hydro_profile_read",
                  "hydro_set_option", "hydro_get_option", "hydro_reset", "hydro_set_jet", "hydro_loss_eps2",
-                 "hydro_adjoint_step", "hydro_init_vjp"):
+                 "hydro_adjoint_step", "hydro_init_vjp", "hydro_sums_noalloc"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -315,6 +316,13 @@ class Hydro:
         out = (ctypes.c_double * 6)()
         self._check(self.lib.hydro_sums(self.ctx, U.data_ptr(), out, _stream_handle(stream)))
         return np.array(list(out))
+
+    def sums_noalloc(self, out, U=None, stream=None):
+        """hydro_sums_noalloc: the sums and the ledger into out (a device
+        float64 tensor of 6 elements), asynchronously, with no allocation."""
+        U = self.U if U is None else U
+        self._check(self.lib.hydro_sums_noalloc(self.ctx, U.data_ptr(), out.data_ptr(), _stream_handle(stream)))
+        return out
 
     def get_state(self):
         t = ctypes.c_double(0)
