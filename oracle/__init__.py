@@ -19,7 +19,14 @@ Parity status per function (pins in tests/test_oracle_*.py):
                    convergence order, exact Riemann solution, energy budget,
                    source closed form)
   sums             pinned (numpy sum)
-  eps2             pinned (closed form on a separable field)
+  eps2             pinned (closed form on a separable field; z = 0 planes
+                   with hot cells next to them)
+  freezeout        pinned (static uniform medium: closed form and v_n = 0;
+                   boosted uniform medium: quadrature of the analytic
+                   spectrum; p_T integral of the differential rows against
+                   the integrated row; isotropic fireball: v_1..v_3 = 0;
+                   mirror images; particle number against the Boltzmann
+                   density's closed form)
   eps2_complex_step pinned (central finite differences of run)
   jvp              pinned (central finite differences of run)
   musta_flux, run with flux="musta"
@@ -114,12 +121,14 @@ def _load():
     lib.oracle_eps2_complex_step.argtypes = [cp, jp, ctypes.c_int, dp, ctypes.c_int, ctypes.c_int,
                                              ctypes.c_int, ctypes.c_double, dp, dp, dp]
     lib.oracle_jvp.argtypes = [cp, jp, ctypes.c_int, dp, dp, ctypes.c_int, ctypes.c_double, dp, dp]
+    lib.oracle_freezeout.argtypes = [cp, dp, ctypes.c_int, ctypes.c_int, dp, ctypes.c_double, ctypes.c_double,
+                                     ctypes.c_int, dp, dp, llp]
     lib.oracle_limit_face.argtypes = [cp, ctypes.c_int, dp, dp, dp, dp]
     lib.oracle_musta_flux.argtypes = [ctypes.c_int, dp, dp, ctypes.c_int, dp, dp, dp]
     lib.oracle_count_flops.argtypes = [ctypes.c_int, ctypes.c_int, llp]
     for name in ("oracle_prim_to_cons", "oracle_cons_to_prim", "oracle_rhs", "oracle_run",
                  "oracle_sums", "oracle_eps2", "oracle_eps2_complex_step", "oracle_jvp", "oracle_limit_face",
-                 "oracle_musta_flux", "oracle_count_flops"):
+                 "oracle_musta_flux", "oracle_count_flops", "oracle_freezeout"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -339,6 +348,28 @@ def jvp(pb: Problem, U0: np.ndarray, V: np.ndarray, nsteps: int, jets=None, h: f
     rc = _load().oracle_jvp(ctypes.byref(c), arr, nj, _dp(U0), _dp(V), int(nsteps), float(h), _dp(Uo), _dp(JV))
     assert rc == 0
     return Uo, JV
+
+
+def freezeout(pb: Problem, U: np.ndarray, n_phi: int = 64, pt=(), T_min: float = 0.0, dof: float = 1.0,
+              n_harm: int = 8):
+    """Cooper-Frye freeze-out of U on its fixed-time surface, massless
+    Boltzmann particles of degeneracy dof, at rapidity 0 along z.  Returns
+    (spectra, harm, fixups): spectra[0, k] = dN/(dy dphi) and
+    spectra[1 + j, k] = dN/(p_T dp_T dy dphi) at p_T = pt[j] [GeV^-2], at
+    phi_k = 2 pi k / n_phi; harm[r, 0, 0] = dN/dy of row r and
+    harm[r, n] = (<cos n phi>, <sin n phi>) of row r."""
+    U = np.ascontiguousarray(U, dtype=np.float64).reshape(5, *pb.shape)
+    pt = np.ascontiguousarray(np.array(pt, dtype=np.float64).reshape(-1))
+    npt = int(pt.size)
+    spec = np.zeros((1 + npt, int(n_phi)))
+    harm = np.zeros((1 + npt, int(n_harm) + 1, 2))
+    fx = ctypes.c_longlong(0)
+    c = pb.c()
+    ptp = _dp(pt) if npt else None
+    rc = _load().oracle_freezeout(ctypes.byref(c), _dp(U), int(n_phi), npt, ptp, float(T_min), float(dof),
+                                  int(n_harm), _dp(spec), _dp(harm), ctypes.byref(fx))
+    assert rc == 0
+    return spec, harm, fx.value
 
 
 def limit_face(pb: Problem, d: int, uA, uB, H):

@@ -799,6 +799,84 @@ S eps2_of(const ocfg& c, const S* U, long long* fixups) {
   return num / den;
 }
 
+// ---------------------------------------------------------------------------
+// Freeze-out, the step the paper plans next (section "Results", closing
+// paragraph: add freeze-out and study elliptic flow and higher harmonics).
+// Cooper-Frye on the fixed-time hypersurface of the state U, d sigma_mu =
+// (dV, 0, 0, 0), emitting a massless Boltzmann species of degeneracy g at
+// zero chemical potential (the quanta of the p = e/3 fluid), T = T(e) of the
+// fluid's equation of state.  At rapidity 0 along z (p_z = 0, p^0 = p_T) a
+// particle of azimuth phi has p.u = gamma p_T (1 - vx cos phi - vy sin phi), so
+//   E dN/d^3p = g / ((2 pi hbar c)^3) sum_cells dV p_T exp(-gamma p_T D / T),
+//   D = 1 - vx cos phi - vy sin phi,
+// and over all p_T (int_0^inf p^2 exp(-a p) dp = 2 / a^3)
+//   dN/(dy dphi) = g / ((2 pi hbar c)^3) sum_cells dV 2 T^3 / (gamma D)^3.
+// Units: p_T and T in GeV, dV in fm^3, hbar c in GeV fm.  Cells with T < T_min
+// are left out (T_min = 0 keeps every cell).  Rows of out ([1 + n_pt][n_phi]):
+// row 0 dN/(dy dphi), row 1 + j dN/(p_T dp_T dy dphi) at p_T = pt[j], each at
+// phi_k = 2 pi k / n_phi.  Per z-plane partial sums, then the planes in order.
+void freezeout_spectra(const ocfg& c, const double* U, int n_phi, int n_pt, const double* pt, double T_min,
+                       double dof, double* out, long long* fixups) {
+  Grid g = make_grid(c);
+  const size_t nc = g.ncell();
+  const double dV = c.dx[0] * c.dx[1] * c.dx[2];
+  const double pref = dof / std::pow(2.0 * kPi * c.hbarc, 3);
+  const int rows = 1 + n_pt;
+  std::vector<double> cphi(n_phi), sphi(n_phi);
+  for (int k = 0; k < n_phi; ++k) {
+    cphi[k] = std::cos(2.0 * kPi * k / n_phi);
+    sphi[k] = std::sin(2.0 * kPi * k / n_phi);
+  }
+  std::vector<double> plane((size_t)g.n[2] * rows * n_phi, 0.0);
+  std::vector<long long> pfx(g.n[2], 0);
+#pragma omp parallel for schedule(static)
+  for (int kz = 0; kz < g.n[2]; ++kz) {
+    double* acc = &plane[(size_t)kz * rows * n_phi];
+    for (int j = 0; j < g.n[1]; ++j) {
+      for (int i = 0; i < g.n[0]; ++i) {
+        const size_t q = g.at(i, j, kz);
+        Prim<double> p = cons_to_prim(U[q], U[nc + q], U[2 * nc + q], U[3 * nc + q], U[4 * nc + q], &pfx[kz]);
+        const double T = temperature(p.e, c);
+        if (T < T_min) continue;
+        const double gam = 1.0 / std::sqrt(1.0 - (p.v[0] * p.v[0] + p.v[1] * p.v[1] + p.v[2] * p.v[2]));
+        for (int k = 0; k < n_phi; ++k) {
+          const double D = 1.0 - p.v[0] * cphi[k] - p.v[1] * sphi[k];
+          const double a = gam * D;
+          acc[k] += pref * dV * 2.0 * T * T * T / (a * a * a);
+          for (int r = 0; r < n_pt; ++r) acc[(size_t)(1 + r) * n_phi + k] += pref * dV * pt[r] * std::exp(-pt[r] * a / T);
+        }
+      }
+    }
+  }
+  for (int o = 0; o < rows * n_phi; ++o) out[o] = 0.0;
+  for (int kz = 0; kz < g.n[2]; ++kz) {
+    for (int o = 0; o < rows * n_phi; ++o) out[o] += plane[(size_t)kz * rows * n_phi + o];
+    if (fixups) *fixups += pfx[kz];
+  }
+}
+
+// Flow harmonics of an azimuthal distribution sampled at phi_k = 2 pi k/n_phi:
+// out[0] = (dN/dy, 0) with dN/dy = (2 pi / n_phi) sum_k s_k (the trapezoid rule
+// of a periodic function), out[n] = (sum_k cos(n phi_k) s_k, sum_k sin(n phi_k)
+// s_k) / sum_k s_k for n = 1..n_harm: v_n is the modulus of that pair and
+// atan2(sin, cos)/n the n-th event-plane angle.
+void flow_harmonics(const double* s, int n_phi, int n_harm, double* out) {
+  double tot = 0.0;
+  for (int k = 0; k < n_phi; ++k) tot += s[k];
+  out[0] = 2.0 * kPi / n_phi * tot;
+  out[1] = 0.0;
+  for (int n = 1; n <= n_harm; ++n) {
+    double cs = 0.0, sn = 0.0;
+    for (int k = 0; k < n_phi; ++k) {
+      const double ang = 2.0 * kPi * (double)(((long long)n * k) % n_phi) / n_phi;
+      cs += std::cos(ang) * s[k];
+      sn += std::sin(ang) * s[k];
+    }
+    out[2 * n] = cs / tot;
+    out[2 * n + 1] = sn / tot;
+  }
+}
+
 template <class S>
 int run_impl(const ocfg* cfg, const ojet* jets, int njet, S* U, int nsteps, long long step0,
              S* Ejet, S* ledger, long long* fixups, const std::vector<Jet<S>>* cjets) {
@@ -928,6 +1006,19 @@ int oracle_eps2(const ocfg* c, const double* U, double* out) {
   if (!valid(c)) return -1;
   long long fx = 0;
   *out = eps2_of<double>(*c, U, &fx);
+  return 0;
+}
+
+// Freeze-out spectra and flow harmonics of U (see freezeout_spectra and
+// flow_harmonics): spectra [1 + n_pt][n_phi], harm [1 + n_pt][n_harm + 1][2].
+int oracle_freezeout(const ocfg* c, const double* U, int n_phi, int n_pt, const double* pt, double T_min,
+                     double dof, int n_harm, double* spectra, double* harm, long long* fixups) {
+  if (!valid(c) || n_phi < 1 || n_pt < 0 || (n_pt > 0 && !pt) || n_harm < 0 || !(dof > 0.0)) return -1;
+  long long fx = 0;
+  freezeout_spectra(*c, U, n_phi, n_pt, pt, T_min, dof, spectra, &fx);
+  for (int r = 0; r <= n_pt; ++r)
+    flow_harmonics(spectra + (size_t)r * n_phi, n_phi, n_harm, harm + (size_t)r * (n_harm + 1) * 2);
+  if (fixups) *fixups = fx;
   return 0;
 }
 
