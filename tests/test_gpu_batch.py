@@ -179,6 +179,27 @@ def test_single_event_x_tile_matches_row_kernel(precision, n):
     assert np.array_equal(outs[0], outs[2]) and np.array_equal(outs[1], outs[3])
 
 
+def test_full_ensemble_with_limiter_has_no_fixups():
+    """The 64-event ensemble for its full 50 steps, FP32, with the
+    positivity-preserving limiter (the reading used for this workload: the
+    unlimited scheme needs recovery fix-ups next to the NGP deposits of 32 of
+    its events, 2063 in all when they run alone); no fix-ups, every final
+    state admissible."""
+    ws = W.ensemble()
+    b = H().batch_from_workloads(ws, precision="f32", limiter="pp")
+    b.autotune(None)
+    b.run(ws[0].steps)
+    torch.cuda.synchronize()
+    assert b.fixups() == 0
+    for e in range(len(ws)):
+        U = b.U[e].double()
+        assert float((U[0] - torch.sqrt(U[1] ** 2 + U[2] ** 2 + U[3] ** 2)).min()) > 0
+        assert float(U[4].min()) > 0
+        t, step, _ = b.get_state(e)
+        assert step == ws[e].steps
+    b.close()
+
+
 def test_full_ensemble_matches_single_events():
     """The 64-event ensemble (edges 64/96/128, 0-3 jets, FP32) for 2 steps,
     every event bitwise equal to its own single-event run."""

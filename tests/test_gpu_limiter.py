@@ -104,6 +104,60 @@ def test_unlimited_gpu_run_needs_the_limiter():
     assert fx > 0 or not admissible(U)
 
 
+def test_unlimited_run_through_the_fixup_branch_matches_oracle():
+    """The unlimited scheme on the peripheral jet: from step 23 on, stage
+    states next to the deposit leave the admissible set and both recoveries
+    take the fix-up branch (M rescaled to the speed cap).  The GPU follows the
+    oracle through it.  Bar per field: max(1e-12, 4 x the oracle's own
+    response to a 1e-15 relative change of the initial e, measured here):
+    the N field next to the deposit is that sensitive (response ~5e-13 of
+    max N from step 24 on), and the GPU's rounding differs from the oracle's
+    in each of the 90 stages, not once.  Observed: E 3.0e-13, N 1.38e-12
+    (3.0 x its response).  (The fix-up counts differ by design: the GPU
+    counts every recovery of a halo point, the oracle each cell once.)"""
+    w = W.peripheral_jet_event()
+    print("peripheral jet, unlimited, FP64", w.n, w.steps, flush=True)
+    st = oracle_run(w, w.steps, limiter="none")
+    assert st.fixups > 0
+    pb = O.Problem(n=w.n, dx=w.dx, t0=w.t0, dt=w.dt, bc=tuple(w.bc), deposit=w.deposit)
+    prim = w.prim0.copy()
+    prim[0] *= 1.0 + 1e-15 * np.random.default_rng(7).uniform(-1.0, 1.0, prim[0].shape)
+    sp = O.run(pb, O.prim_to_cons(pb, prim), w.steps, [O.Jet(**j.__dict__) for j in w.jets])
+    bar = np.maximum(1e-12, 4.0 * rel_linf(sp.U, st.U))
+    U, fx, (_, step, Ej) = gpu_run(w, w.steps, limiter="none")
+    err = rel_linf(U, st.U)
+    print("rel Linf", err, "bar", bar, "fix-ups gpu", fx, "oracle", st.fixups, flush=True)
+    assert fx > 0
+    assert np.all(err <= bar), (err, bar)
+    assert Ej[0] == pytest.approx(st.Ejet[0], rel=1e-12)
+
+
+@pytest.mark.parametrize("n,njets,precision", [((256, 256, 256), 1, "f64"), ((256, 256, 256), 3, "f32"),
+                                               ((512, 512, 512), 3, "f32")])
+def test_fp32_event_needs_no_fixups_with_the_limiter(n, njets, precision):
+    """The small event's initial state on the large grids with 1-3 jets, the
+    full run (256^3: 120 steps; 512^3: 60).  Unlimited, the NGP deposit (a
+    light-like spike into one cell every step) drives stage states next to it
+    out of the admissible set after 14-33 steps (fix-ups > 0, measured); with
+    the positivity-preserving limiter, the reading used for this workload,
+    there is none, and every cell of the final state is admissible."""
+    w = W.fp32_event(3, n=n, njets=njets)
+    print("fp32_event", n, njets, precision, w.steps, flush=True)
+    h = H().from_workload(w, precision=precision, limiter="pp")
+    h.step(w.steps)
+    torch.cuda.synchronize()
+    assert h.fixups() == 0
+    E = h.U[0].double()
+    M = torch.sqrt(h.U[1].double() ** 2 + h.U[2].double() ** 2 + h.U[3].double() ** 2)
+    assert float((E - M).min()) > 0 and float(h.U[4].min()) > 0
+    h.close()
+    hu = H().from_workload(w, precision=precision, limiter="none")
+    hu.step(w.steps)
+    print("unlimited fix-ups", hu.fixups(), flush=True)
+    assert hu.fixups() > 0
+    hu.close()
+
+
 @pytest.mark.parametrize("axis", [0, 1, 2])
 def test_vacuum_riemann_matches_oracle(axis):
     # e_R = 1e-7: the unlimited scheme leaves E < |M| and N < 0 (oracle);
