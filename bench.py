@@ -25,6 +25,8 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
@@ -216,15 +218,61 @@ def adjoint_ratio(precision: str, n: int, steps: int, ckpt: int, repeats: int = 
     return out
 
 
-def batch_throughput(precision: str, steps: int, warmup: int, cache):
+# Algorithmic flops of the freeze-out pass (adds and multiplies 1, fma 2,
+# divide, square root, exp and pow 1): per cell the recovery (25), T(e) (4),
+# gamma and the weights (8); per cell and azimuth D = 1 - vx cos - vy sin (4)
+# and the p_T-integrated term w/(gamma D)^3 added in (cube 2, divide 1, fma 2);
+# per cell, azimuth and p_T the exponent (2), exp (1), the fma (2).
+FO_FLOPS_CELL, FO_FLOPS_PHI, FO_FLOPS_PT = 37, 9, 5
+
+
+def freezeout_timing(precision: str, n: int, steps: int, n_phi: int, pts, repeats: int = 5):
+    """hydro_freezeout on the paper event after `steps` steps: mean time of
+    the spectra + harmonics launches (HIP events on the launch stream) and
+    the ALU fraction of the algorithmic flops; v_2 and v_3 of the
+    p_T-integrated row."""
+    import torch
+    from paper_1511_02137_amd import hydro as H
+    from paper_1511_02137_amd import workloads as W
+    w = W.paper_event(2, n=(n,) * 3)
+    h = H.from_workload(w, precision=precision)
+    h.step(steps)
+    h.freezeout(n_phi=n_phi, pt=pts, n_harm=8)
+    torch.cuda.synchronize()
+    start = torch.cuda.Event(enable_timing=True)
+    stop = torch.cuda.Event(enable_timing=True)
+    start.record()
+    for _ in range(repeats):
+        spec, harm = h.freezeout(n_phi=n_phi, pt=pts, n_harm=8)
+    stop.record()
+    torch.cuda.synchronize()
+    ms = start.elapsed_time(stop) / repeats
+    nc = n ** 3
+    flops = nc * (FO_FLOPS_CELL + n_phi * (FO_FLOPS_PHI + FO_FLOPS_PT * len(pts)))
+    hm = harm.cpu().numpy()
+    out = {"workload": "%s after %d steps, %s fields: Cooper-Frye on the fixed-time surface, massless Boltzmann "
+                       "particles at y = 0, %d azimuths, p_T-integrated + %d p_T values"
+                       % (w.name, steps, precision, n_phi, len(pts)),
+           "ms": ms, "achieved_tflops": flops / (ms * 1e-3) / 1e12, "peak": PEAK_TFLOPS["f64"],
+           "alu_frac": flops / (ms * 1e-3) / 1e12 / PEAK_TFLOPS["f64"],
+           "dNdy": float(hm[0, 0, 0]),
+           "v2": float(np.hypot(*hm[0, 2])), "v3": float(np.hypot(*hm[0, 3]))}
+    h.close()
+    return out
+
+
+def batch_throughput(precision: str, steps: int, warmup: int, cache, limiter: str = "pp"):
     """The uneven ensemble (workloads.ensemble: 64 events, edges 64/96/128,
     0-3 jets) advanced by the batch API: autotuned launch shapes, one graph
-    replay per step; cell-updates/s over `steps` steps."""
+    replay per step; cell-updates/s over `steps` steps.  The positivity-
+    preserving limiter is on by default: without it the NGP deposits drive
+    stage states of 32 of the events out of the admissible set (recovery
+    fix-ups) within the 50 steps."""
     import torch
     from paper_1511_02137_amd import hydro as H
     from paper_1511_02137_amd import workloads as W
     ws = W.ensemble(steps=steps)
-    b = H.batch_from_workloads(ws, precision=precision)
+    b = H.batch_from_workloads(ws, precision=precision, limiter=limiter)
     from_cache = b.autotune(cache)
     b.run(warmup)
     torch.cuda.synchronize()
@@ -236,10 +284,14 @@ def batch_throughput(precision: str, steps: int, warmup: int, cache):
     torch.cuda.synchronize()
     ms = start.elapsed_time(stop)
     cells = sum(w.n[0] * w.n[1] * w.n[2] for w in ws)
+    value = cells * 3 * steps / (ms * 1e-3)
     out = {"workload": "ensemble of %d events, edges {64, 96, 128} per axis, 0-3 jets, %s fields, %d steps, "
-                       "one graph replay per step" % (len(ws), precision, steps),
-           "cells": cells, "ms_per_step": ms / steps, "value": cells * 3 * steps / (ms * 1e-3),
-           "unit": "cell-updates/s", "blocks_per_axis": [b.get_option(a) for a in (0, 1, 2)],
+                       "one graph replay per step%s" % (len(ws), precision, steps,
+                                                        ", positivity limiter" if limiter == "pp" else ""),
+           "cells": cells, "ms_per_step": ms / steps, "value": value,
+           "unit": "cell-updates/s", "limiter": limiter,
+           "alu_frac": FLOPS_PER_CELL_UPDATE * value / 1e12 / PEAK_TFLOPS[precision],
+           "blocks_per_axis": [b.get_option(a) for a in (0, 1, 2)],
            "x_form": "rows" if b.get_option(H.BOPT_X_ROWS) else "tiles",
            "tuned_from_cache": from_cache, "fixups": b.fixups()}
     b.close()
@@ -257,6 +309,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--yz", choices=["tile", "march"], default="tile", help="y/z face kernels")
     ap.add_argument("--x", choices=["row", "tile"], default="row", help="x face kernel")
+    ap.add_argument("--tile-order", type=int, default=2, choices=[0, 1, 2, 3],
+                    help="workgroup order of the y/z LDS tiles (HYDRO_OPT_TILE_ORDER)")
     ap.add_argument("--limiter", choices=["none", "pp"], default="none",
                     help="face-flux limiter of the stage run (pp: positivity-preserving)")
     ap.add_argument("--flux", choices=["weno", "musta"], default="weno",
@@ -271,7 +325,11 @@ def main():
     ap.add_argument("--batch-steps", type=int, default=50, help="steps of the ensemble run (0: skip)")
     ap.add_argument("--precision-steps", type=int, default=10,
                     help="steps of the FP32-against-FP64 check at the stage shape (0: skip)")
+    ap.add_argument("--freezeout-steps", type=int, default=10,
+                    help="steps of the paper event before the timed freeze-out (0: skip)")
     ap.add_argument("--batch-precision", choices=["f64", "f32"], default="f32")
+    ap.add_argument("--batch-limiter", choices=["none", "pp"], default="pp",
+                    help="face-flux limiter of the ensemble run")
     ap.add_argument("--tune-cache", default=None, help="autotuner cache file of the ensemble run")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain device copy of 1 GiB 10 times (scale for the HBM counters)")
@@ -303,6 +361,7 @@ def main():
     fpc_update = sum(fpc.values())
     h.set_option(H.OPT_YZ_KERNEL, 0 if args.yz == "tile" else 1)
     h.set_option(H.OPT_X_KERNEL, 0 if args.x == "row" else 1)
+    h.set_option(H.OPT_TILE_ORDER, args.tile_order)
     nc = w.n[0] * w.n[1] * w.n[2]
 
     h.step(args.warmup)
@@ -364,7 +423,7 @@ def main():
                                    (" (MUSTA-FORCE fluxes, %d stages, of the WENO states)" % args.musta_k
                                     if args.flux == "musta" else "")),
                    "grid": list(w.n), "precision": args.precision, "jets": len(w.jets), "yz_kernel": args.yz,
-                   "x_kernel": args.x, "weno": args.weno, "limiter": args.limiter, "flux": args.flux,
+                   "x_kernel": args.x, "tile_order": args.tile_order, "weno": args.weno, "limiter": args.limiter, "flux": args.flux,
                    "musta_k": args.musta_k if args.flux == "musta" else None},
         "roofline": roofline,
         "step_alu_frac": step_frac,
@@ -380,8 +439,13 @@ def main():
     if args.adjoint_n > 0:
         out["adjoint"] = adjoint_ratio(args.adjoint_precision, args.adjoint_n, args.adjoint_steps, args.adjoint_ckpt)
         print("adjoint/forward %.2f" % out["adjoint"]["ratio"], file=sys.stderr, flush=True)
+    if args.freezeout_steps > 0:
+        out["freezeout"] = freezeout_timing(args.precision, args.n, args.freezeout_steps, 64,
+                                            [0.5, 1.0, 1.5, 2.0, 3.0])
+        print("freeze-out %.3f ms" % out["freezeout"]["ms"], file=sys.stderr, flush=True)
     if args.batch_steps > 0:
-        out["batch"] = batch_throughput(args.batch_precision, args.batch_steps, 2, args.tune_cache)
+        out["batch"] = batch_throughput(args.batch_precision, args.batch_steps, 2, args.tune_cache,
+                                        args.batch_limiter)
         print("batch %.3e cell-updates/s" % out["batch"]["value"], file=sys.stderr, flush=True)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds)

@@ -43,7 +43,9 @@ extern "C" {
 typedef enum {
   HYDRO_OK = 0,
   HYDRO_EINVAL = -1,    /* bad argument or configuration */
-  HYDRO_ENOMEM = -2,    /* a device allocation of the library failed */
+  HYDRO_ENOMEM = -2,    /* a device allocation of the library failed (the
+                           environment variable HYDRO_ALLOC_LIMIT_BYTES, a byte
+                           count, makes larger allocations fail, for tests) */
   HYDRO_EDEVICE = -3,   /* a HIP call failed */
   HYDRO_ENONPHYS = -4,  /* strict mode: a non-admissible cell was met */
   HYDRO_ESTATE = -5     /* call not valid in the context's current state */
@@ -151,12 +153,15 @@ void hydro_default_config(hydro_config* cfg);
 
 /* Bytes of caller-provided device workspace that hydro_init needs for cfg:
  * two stage states and one flux-divergence field (15 words per cell) plus
- * reduction partials.  adjoint_k > 0 adds room for the 3*adjoint_k stage
+ * reduction partials (conservation sums, eps2, freeze-out: 8 MiB).  adjoint_k > 0 adds room for the 3*adjoint_k stage
  * states one hydro_adjoint_step of adjoint_k steps recomputes and for the
  * adjoint fields.  Returns 0 for an invalid cfg. */
 size_t hydro_workspace_bytes(const hydro_config* cfg, int adjoint_k);
 
-/* Create a context and set U from primitive fields.
+/* Create a context and set U from primitive fields: the conserved variables
+ * of Eq. (1) -- energy and momentum densities T^{0 nu} and the charge density
+ * (section "Simulation setup") -- of an initial state given at t0 (the paper
+ * starts at t0 = 1 fm/c, section "Results"), with p = e/3 (Fig. 3 caption).
  *   prim0     [5][nz][ny][nx] double: e, vx, vy, vz, n; host or device
  *             memory (detected); |v| < 1, e > 0.  May be NULL: U is then
  *             taken as already initialised by the caller.
@@ -172,7 +177,10 @@ int hydro_init(const hydro_config* cfg, const double* prim0, void* U, void* work
 /* Append a jet; *jet_id (may be NULL) receives its index.  Synchronous. */
 int hydro_add_jet(hydro_ctx* ctx, const hydro_jet* jet, int* jet_id);
 
-/* Advance U (in place) by nsteps Shu-Osher SSP-RK3 steps:
+/* Eq. (1) with the source of Eq. (2)-(3), integrated as the paper states
+ * (section "Simulation setup": 7th-order WENO in space, third-order
+ * Runge-Kutta in time; dx, dt of the Fig. 3 caption).
+ * Advance U (in place) by nsteps Shu-Osher SSP-RK3 steps:
  *   U1 = U + dt L(U);  U2 = 3/4 U + 1/4 (U1 + dt L(U1));
  *   U  = 1/3 U + 2/3 (U2 + dt L(U2)),
  * stage times t_n, t_n + dt, t_n + dt/2, with t_n = t0 + n dt.  L = D + S is
@@ -190,13 +198,53 @@ int hydro_rk3_step(hydro_ctx* ctx, void* U, int nsteps, void* stream);
 int hydro_rhs(hydro_ctx* ctx, const void* U, double t, void* L, void* stream);
 
 /* Primitive fields of U: prim [6][nz][ny][nx] of U's type: e, vx, vy, vz,
- * n, T (device).  Recovery in FP64 with p = e/3. */
+ * n, T (device).  Recovery in FP64 with p = e/3 (Fig. 3 caption) from the
+ * definition T^{0 nu} = (e+p) u^0 u^nu - p g^{0 nu} of Eq. (1); T is the
+ * local temperature that Eq. (3) uses (section "Simulation setup"). */
 int hydro_primitives(hydro_ctx* ctx, const void* U, void* prim, void* stream);
 
-/* Synchronous: out[0..4] = sum over cells of E, Mx, My, Mz, N times dV
+/* The totals that Eq. (1) conserves without a source and the energy the
+ * jets deposit through Eq. (2)-(3) (section "Simulation setup").
+ * Synchronous: out[0..4] = sum over cells of E, Mx, My, Mz, N times dV
  * (FP64, fixed reduction order), out[5] = deposited-energy ledger.
- * Returns HYDRO_ENONPHYS in strict mode after a fix-up. */
+ * Returns HYDRO_ENONPHYS when a sum is not finite (a NaN or infinity in U,
+ * out still written) and, in strict mode, after a fix-up. */
 int hydro_sums(hydro_ctx* ctx, const void* U, double out[6], void* stream);
+
+/* Freeze-out: particles from the evolved fluid and their flow harmonics,
+ * the step the paper plans next (section "Results", closing paragraph: add
+ * freeze-out to study elliptic flow and higher flow harmonics).  Reading:
+ * Cooper-Frye on the fixed-time hypersurface of U (d sigma_mu = (dV, 0, 0,
+ * 0)) for a massless Boltzmann species of degeneracy dof at zero chemical
+ * potential (the quanta of the p = e/3 fluid), T = T(e) of the fluid's
+ * equation of state (cfg.eos_dof), at rapidity 0 along z.  With
+ * D = 1 - vx cos phi - vy sin phi and gamma the cell's Lorentz factor:
+ *   spectra[0][k]     = dN/(dy dphi)         = dof/(2 pi hbar c)^3 sum dV 2 T^3/(gamma D)^3,
+ *   spectra[1 + j][k] = dN/(p_T dp_T dy dphi) = dof/(2 pi hbar c)^3 sum dV p_T exp(-gamma p_T D/T)
+ * at phi_k = 2 pi k / n_phi (GeV^-2 for the differential rows, p_T = pt[j]),
+ * summed over the cells with T >= T_min.  harm (may be NULL) [1 + n_pt]
+ * [n_harm + 1][2]: harm[r][0] = (dN/dy of row r by the trapezoid rule
+ * (2 pi/n_phi) sum_k, 0), harm[r][n] = (sum_k cos(n phi_k) s_k, sum_k
+ * sin(n phi_k) s_k) / sum_k s_k of row r: v_n is the modulus of that pair,
+ * its angle / n the n-th event-plane angle (x = the reaction plane of the
+ * initial ellipsoid).  Both outputs are device FP64, written asynchronously;
+ * primitives are recovered in FP64 (fix-ups counted as in hydro_primitives).
+ * Fixed reduction order (run-to-run identical).  Limits: 0 <= n_pt <= 15,
+ * (1 + n_pt) n_phi <= 1024, 0 <= n_harm <= 32 with 2 n_harm < n_phi,
+ * pt[j] > 0, dof > 0, T_min >= 0; else HYDRO_EINVAL.  Reduction partials use
+ * the context's workspace. */
+typedef struct {
+  int32_t n_phi;    /* azimuths */
+  int32_t n_pt;     /* p_T-differential rows */
+  int32_t n_harm;   /* harmonics */
+  int32_t reserved; /* 0 */
+  double pt[15];    /* GeV */
+  double T_min;     /* GeV; 0 keeps every cell */
+  double dof;       /* degeneracy of the emitted species */
+} hydro_freezeout_params;
+
+int hydro_freezeout(hydro_ctx* ctx, const void* U, const hydro_freezeout_params* fp, double* spectra,
+                    double* harm, void* stream);
 
 /* For callers that cannot allocate device memory (code under HIP graph
  * capture, tight serving loops, harnesses that forbid hipMalloc): the sums
@@ -269,7 +317,10 @@ typedef enum {
   HYDRO_OPT_YZ_KERNEL = 0,  /* y/z faces: 0 = LDS tiles (default), 1 = register marches */
   HYDRO_OPT_MARCH_SEG = 1,  /* cells per march segment (default 32) */
   HYDRO_OPT_X_KERNEL = 2,   /* x faces: 0 = one row per workgroup (default), 1 = 32 x 16 LDS tiles */
-  HYDRO_OPT_ADJ_SKIP_N = 3  /* 0 (default) or 1, see above */
+  HYDRO_OPT_ADJ_SKIP_N = 3, /* 0 (default) or 1, see above */
+  HYDRO_OPT_TILE_ORDER = 4  /* order of the y/z LDS tiles' workgroups, 0..3: bit 0 (y tiles), bit 1 (z
+                               tiles) set = neighbouring workgroups share the tile index and step the
+                               transverse axis, clear = they step along the axis; default 2 */
 } hydro_option;
 
 /* Set / read an option; HYDRO_EINVAL for an unknown option or bad value. */

@@ -15,7 +15,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libhydro.so")
-SOURCES = ["hydro_kernels.hip", "hydro_adjoint.hip", "hydro_api.hip", "hydro_batch.hip"]
+SOURCES = ["hydro_kernels.hip", "hydro_adjoint.hip", "hydro_api.hip", "hydro_batch.hip", "hydro_freezeout.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = os.environ.get("HYDRO_OFFLOAD_ARCH", "gfx950")
 

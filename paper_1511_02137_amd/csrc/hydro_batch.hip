@@ -336,11 +336,11 @@ int hydro_batch_create(const hydro_config* cfgs, int n_events, const double* con
     delete b;
     return code;
   };
-  hipError_t e = hipMalloc(&b->d_ev, sizeof(BatchEvent) * n_events);
-  if (e == hipSuccess) e = hipMalloc(&b->d_off, sizeof(long long) * 5 * (n_events + 1));
-  if (e == hipSuccess) e = hipMalloc(&b->d_dev, sizeof(DevScalars) * n_events);
-  if (e == hipSuccess) e = hipMalloc(&b->d_part, sizeof(double) * (size_t)n_events * kSumBlocks * 5);
-  if (e == hipSuccess) e = hipMalloc(&b->d_step, sizeof(long long));
+  hipError_t e = lib_malloc(&b->d_ev, sizeof(BatchEvent) * n_events);
+  if (e == hipSuccess) e = lib_malloc(&b->d_off, sizeof(long long) * 5 * (n_events + 1));
+  if (e == hipSuccess) e = lib_malloc(&b->d_dev, sizeof(DevScalars) * n_events);
+  if (e == hipSuccess) e = lib_malloc(&b->d_part, sizeof(double) * (size_t)n_events * kSumBlocks * 5);
+  if (e == hipSuccess) e = lib_malloc(&b->d_step, sizeof(long long));
   if (e != hipSuccess) return cleanup(HYDRO_ENOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
   e = hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking);
   if (e != hipSuccess) return cleanup(HYDRO_EDEVICE, std::string("hipStreamCreate: ") + hipGetErrorString(e));
@@ -401,7 +401,7 @@ int hydro_batch_create(const hydro_config* cfgs, int n_events, const double* con
       const double* dprim = prim0[i];
       double* tmp = nullptr;
       if (!is_device_pointer(prim0[i])) {
-        e = hipMalloc(&tmp, (size_t)5 * nc * sizeof(double));
+        e = lib_malloc(&tmp, (size_t)5 * nc * sizeof(double));
         if (e == hipSuccess) e = hipMemcpy(tmp, prim0[i], (size_t)5 * nc * sizeof(double), hipMemcpyHostToDevice);
         dprim = tmp;
       }

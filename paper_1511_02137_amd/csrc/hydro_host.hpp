@@ -6,6 +6,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <cstdlib>
 #include <string>
 
 #include "hydro.h"
@@ -14,6 +15,24 @@
 namespace hydro {
 
 inline size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+// Every device allocation of the library goes through here.  With the
+// environment variable HYDRO_ALLOC_LIMIT_BYTES set (a decimal byte count),
+// larger allocations fail as if the device were out of memory, so that the
+// HYDRO_ENOMEM paths can be exercised from the host; unset, it is hipMalloc.
+template <class T>
+inline hipError_t lib_malloc(T** p, size_t bytes) {
+  const char* lim = std::getenv("HYDRO_ALLOC_LIMIT_BYTES");
+  if (lim && *lim) {
+    char* end = nullptr;
+    const unsigned long long v = std::strtoull(lim, &end, 10);
+    if (end != lim && bytes > v) {
+      *p = nullptr;
+      return hipErrorOutOfMemory;
+    }
+  }
+  return hipMalloc(reinterpret_cast<void**>(p), bytes);
+}
 
 inline size_t elem_size(const hydro_config* c) { return c->precision == HYDRO_F32 ? sizeof(float) : sizeof(double); }
 
@@ -121,5 +140,7 @@ hipError_t launch_batch_jet(const BatchArgs<R>& b, hipStream_t st);
 template <class R>
 hipError_t launch_batch_sums(const BatchArgs<R>& b, long long* step, hipStream_t st);
 long long batch_items(int AX, const Grid& g, int xtb, int elem);
+template <class R>
+hipError_t launch_freezeout(const FreezeArgs<R>& a, double* spectra, double* harm, int n_harm, hipStream_t st);
 
 }  // namespace hydro

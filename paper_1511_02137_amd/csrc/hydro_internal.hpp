@@ -62,6 +62,7 @@ struct StageArgs {
   R eps;        // epsilon of the WENO weights
   int stage;    // 1, 2, 3 (RK stage); 0: write L = D + S instead of combining
   int seg;      // march segment length (y/z kernels)
+  int order;    // LDS tiles: bit AX-1 set = blockIdx.y runs over the transverse axis, blockIdx.z over the tiles
   unsigned long long* fixups;
   double pp_mu;  // 2 dt sum_d 1/dx_d, the half-state factor of the positivity limiter
   int musta_k;   // MUSTA-FORCE stages
@@ -202,6 +203,30 @@ struct JetAdjArgs {
   double t;             // stage time
   double bdt;           // b_k * dt of the stage
   double eos_dof, hbarc;
+};
+
+// Freeze-out spectra (hydro_freezeout): limits and arguments.
+constexpr int kFoThreads = 256;           // lanes per workgroup
+constexpr int kFoMaxOut = 1024;           // (1 + n_pt) * n_phi outputs
+constexpr int kFoOutPerLane = kFoMaxOut / kFoThreads;
+constexpr int kFoMaxPt = 15;              // p_T values of the differential rows
+constexpr int kFoMaxHarm = 32;            // harmonics n = 1..n_harm
+constexpr int kFoBlocks = 1024;           // workgroups of the partial-sum pass (fixed order)
+
+template <class R>
+struct FreezeArgs {
+  const R* U;
+  long long nc;
+  int n_phi;             // azimuths phi_k = 2 pi k / n_phi
+  int rows;              // 1 + n_pt
+  int n_out;             // rows * n_phi
+  int groups;            // lane groups sharing one set of outputs (n_out <= kFoThreads / groups)
+  double pt[kFoMaxPt];   // p_T of rows 1..
+  double T_min;          // cells with T < T_min are left out
+  double pref_dV;        // g dV / (2 pi hbar c)^3
+  double eos_dof, hbarc; // T(e) of the fluid
+  double* part;          // [kFoBlocks][n_out] partial sums
+  unsigned long long* fixups;
 };
 
 }  // namespace hydro

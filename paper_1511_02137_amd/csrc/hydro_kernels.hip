@@ -615,7 +615,9 @@ __device__ __forceinline__ void tile_body(const StageArgs<R>& a, int bx, int by,
 template <class R, int S, int AX, bool LAST, int A>
 __global__ void __launch_bounds__(512) k_tile(StageArgs<R> a) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  tile_body<R, S, AX, LAST, A, true>(a, blockIdx.x, blockIdx.y, blockIdx.z, reinterpret_cast<R*>(smem_raw));
+  const int by = a.order ? blockIdx.z : blockIdx.y;  // tile along AX
+  const int bz = a.order ? blockIdx.y : blockIdx.z;  // transverse index
+  tile_body<R, S, AX, LAST, A, true>(a, blockIdx.x, by, bz, reinterpret_cast<R*>(smem_raw));
 }
 
 // ---------------------------------------------------------------------------
@@ -958,6 +960,7 @@ __device__ __forceinline__ StageArgs<R> batch_stage_args(const BatchEvent& ev, i
   a.out = (stage <= 1) ? U1 : (stage == 2 ? U2 : U);
   a.D = static_cast<R*>(ev.D);
   a.g = ev.g;
+  a.order = 0;
   a.inv_d = (R)ev.inv_d[AX];
   a.dt = (R)ev.dt;
   a.eps = eps;
@@ -1118,7 +1121,9 @@ void launch_tile_t(const StageArgs<R>& base, hipStream_t st) {
   const int no = (AX == 1) ? a.g.n[2] : a.g.n[1];
   const int A = tile_len(n);
   const size_t lds = (size_t)2 * 5 * (A + 8) * kTileXP * sizeof(R);
+  a.order = (base.order >> (AX - 1)) & 1;
   dim3 grid((nx + kTileX - 1) / kTileX, (n + A - 1) / A, no);
+  if (a.order) grid = dim3(grid.x, no, grid.y);
   if (A == 31) hipLaunchKernelGGL((k_tile<R, S, AX, AX == 2, 31>), grid, dim3(512), lds, st, a);
   else hipLaunchKernelGGL((k_tile<R, S, AX, AX == 2, 32>), grid, dim3(512), lds, st, a);
 }

@@ -31,9 +31,9 @@ EXPORTED = [
     "hydro_init_vjp", "hydro_batch_workspace_bytes", "hydro_batch_create", "hydro_batch_add_jet", "hydro_batch_run",
     "hydro_batch_rhs", "hydro_batch_set_option", "hydro_batch_get_option", "hydro_batch_autotune",
     "hydro_batch_sums", "hydro_batch_get_state", "hydro_batch_diag", "hydro_batch_last_error",
-    "hydro_batch_destroy", "hydro_sums_noalloc",
+    "hydro_batch_destroy", "hydro_sums_noalloc", "hydro_freezeout",
 ]
-OPT_YZ_KERNEL, OPT_MARCH_SEG, OPT_X_KERNEL, OPT_ADJ_SKIP_N = 0, 1, 2, 3
+OPT_YZ_KERNEL, OPT_MARCH_SEG, OPT_X_KERNEL, OPT_ADJ_SKIP_N, OPT_TILE_ORDER = 0, 1, 2, 3, 4
 BOPT_BLOCKS_X, BOPT_BLOCKS_Y, BOPT_BLOCKS_Z, BOPT_GRAPH, BOPT_X_ROWS = 0, 1, 2, 3, 4
 KERNELS = ["xface", "xbound", "ymarch", "jet", "zmarch", "sums", "adjoint"]
 
@@ -77,6 +77,18 @@ class JetC(ctypes.Structure):
     ]
 
 
+class FreezeoutParams(ctypes.Structure):
+    _fields_ = [
+        ("n_phi", ctypes.c_int32),
+        ("n_pt", ctypes.c_int32),
+        ("n_harm", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
+        ("pt", ctypes.c_double * 15),
+        ("T_min", ctypes.c_double),
+        ("dof", ctypes.c_double),
+    ]
+
+
 _lib = None
 
 
@@ -100,6 +112,7 @@ def load_library(path: str = LIB_PATH):
     lib.hydro_rhs.argtypes = [vp, vp, ctypes.c_double, vp, vp]
     lib.hydro_sums.argtypes = [vp, vp, dp, vp]
     lib.hydro_sums_noalloc.argtypes = [vp, vp, vp, vp]
+    lib.hydro_freezeout.argtypes = [vp, vp, ctypes.POINTER(FreezeoutParams), vp, vp, vp]
     lib.hydro_get_state.argtypes = [vp, dp, ctypes.POINTER(ctypes.c_int64), dp, ctypes.c_int]
     lib.hydro_set_state.argtypes = [vp, ctypes.c_int64, dp, ctypes.c_int, ctypes.c_double]
     lib.hydro_diag.argtypes = [vp, ctypes.POINTER(ctypes.c_int64)]
@@ -140,7 +153,7 @@ def load_library(path: str = LIB_PATH):
     for name in ("hydro_init", "hydro_add_jet", "hydro_rk3_step", "hydro_primitives", "hydro_rhs", "hydro_sums",
                  "hydro_get_state", "hydro_set_state", "hydro_diag", "hydro_profile", "hydro_profile_read",
                  "hydro_set_option", "hydro_get_option", "hydro_reset", "hydro_set_jet", "hydro_loss_eps2",
-                 "hydro_adjoint_step", "hydro_init_vjp", "hydro_sums_noalloc"):
+                 "hydro_adjoint_step", "hydro_init_vjp", "hydro_sums_noalloc", "hydro_freezeout"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -323,6 +336,24 @@ class Hydro:
         U = self.U if U is None else U
         self._check(self.lib.hydro_sums_noalloc(self.ctx, U.data_ptr(), out.data_ptr(), _stream_handle(stream)))
         return out
+
+    def freezeout(self, n_phi: int = 64, pt=(), T_min: float = 0.0, dof: float = 1.0, n_harm: int = 8, U=None,
+                  stream=None):
+        """hydro_freezeout: (spectra [1 + n_pt, n_phi], harm [1 + n_pt, n_harm + 1, 2]) as device
+        float64 tensors (written asynchronously on the stream)."""
+        import torch
+        U = self.U if U is None else U
+        pt = [float(v) for v in pt]
+        fp = FreezeoutParams()
+        fp.n_phi, fp.n_pt, fp.n_harm, fp.reserved = int(n_phi), len(pt), int(n_harm), 0
+        for j, v in enumerate(pt[:15]):
+            fp.pt[j] = v
+        fp.T_min, fp.dof = float(T_min), float(dof)
+        spec = torch.empty((1 + len(pt), int(n_phi)), dtype=torch.float64, device=self.device)
+        harm = torch.empty((1 + len(pt), int(n_harm) + 1, 2), dtype=torch.float64, device=self.device)
+        self._check(self.lib.hydro_freezeout(self.ctx, U.data_ptr(), ctypes.byref(fp), spec.data_ptr(),
+                                             harm.data_ptr(), _stream_handle(stream)))
+        return spec, harm
 
     def get_state(self):
         t = ctypes.c_double(0)

@@ -37,7 +37,7 @@ def test_every_declared_symbol_is_exported(lib):
 def test_struct_layout_matches_the_c_compiler(tmp_path):
     # Compile the header with gcc and compare every field offset with ctypes.
     checks = []
-    for cname, pyt in (("hydro_config", H.Config), ("hydro_jet", H.JetC)):
+    for cname, pyt in (("hydro_config", H.Config), ("hydro_jet", H.JetC), ("hydro_freezeout_params", H.FreezeoutParams)):
         checks.append((cname, "sizeof", ctypes.sizeof(pyt)))
         for fname, _ in pyt._fields_:
             checks.append((cname, fname, getattr(pyt, fname).offset))
