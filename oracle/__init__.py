@@ -48,7 +48,9 @@ from typing import Sequence
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-_LIB_PATH = os.path.join(_HERE, "libhydro_oracle.so")
+# HYDRO_ORACLE_LIB names another build of the same source (the sanitized one
+# that oracle/build_oracle.py --sanitize writes), for a child process only.
+_LIB_PATH = os.environ.get("HYDRO_ORACLE_LIB") or os.path.join(_HERE, "libhydro_oracle.so")
 _lib = None
 
 
@@ -94,8 +96,9 @@ def _load():
     global _lib
     if _lib is not None:
         return _lib
-    if not os.path.exists(_LIB_PATH) or os.path.getmtime(_LIB_PATH) < os.path.getmtime(
-            os.path.join(_HERE, "hydro_oracle.cpp")):
+    stale = not os.path.exists(_LIB_PATH) or os.path.getmtime(_LIB_PATH) < os.path.getmtime(
+        os.path.join(_HERE, "hydro_oracle.cpp"))
+    if stale and not os.environ.get("HYDRO_ORACLE_LIB"):
         from . import build_oracle
         build_oracle.build()
     lib = ctypes.CDLL(_LIB_PATH)
