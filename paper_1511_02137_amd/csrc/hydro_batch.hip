@@ -44,6 +44,7 @@ struct hydro_batch {
   int cus = 256;
   long long blocks[3] = {0, 0, 0}; // workgroups per axis launch (0: one per item)
   int xrows = 0;                   // x pass: 0 LDS tiles, 1 groups of whole rows (+ boundary faces)
+  int tile_a[3] = {0, 0, 0};       // per axis: the tile length every event shares (31, 32), else 0
   int xtb = 256;                   // x-row workgroup size
   long long xlds = 0;              // its dynamic LDS
   int use_graph = 1;
@@ -93,6 +94,7 @@ BatchArgs<R> batch_args(const hydro_batch* b, int AX, int stage) {
   a.eps = (R)b->cfg[0].weno_eps;
   a.xtb = b->xtb;
   a.xlds = b->xlds;
+  a.tile_a = AX <= 2 ? b->tile_a[AX] : 0;
   return a;
 }
 
@@ -353,6 +355,12 @@ int hydro_batch_create(const hydro_config* cfgs, int n_events, const double* con
     for (int i = 0; i < n_events; ++i) nxs[i] = cfgs[i].n[0];
     const int elem = (int)elem_size(&cfgs[0]);
     b->xtb = xrow_block(nxs.data(), n_events, elem);
+    for (int AX = 0; AX < 3; ++AX) {
+      int A = tile_len(cfgs[0].n[AX]);
+      for (int i = 1; i < n_events; ++i)
+        if (tile_len(cfgs[i].n[AX]) != A) A = 0;
+      b->tile_a[AX] = A;
+    }
     b->xlds = 0;
     for (int i = 0; i < n_events; ++i)
       b->xlds = std::max<long long>(b->xlds, (long long)xrow_lds_bytes(nxs[i], xrow_rows(nxs[i], b->xtb, elem), elem));

@@ -33,7 +33,9 @@ namespace hydro {
 
 namespace {
 
-template <class R>
+// OPL: outputs per lane, ceil(n_out / 256) rounded up to 1, 2 or 4 (its
+// arrays live in registers: fewer outputs, more waves).
+template <class R, int OPL>
 __global__ void __launch_bounds__(kFoThreads) k_fo_partial(FreezeArgs<R> a) {
   __shared__ double s_w[kFoThreads], s_vx[kFoThreads], s_vy[kFoThreads], s_gt[kFoThreads], s_wp[kFoThreads];
   __shared__ double s_red[kFoThreads];
@@ -43,11 +45,11 @@ __global__ void __launch_bounds__(kFoThreads) k_fo_partial(FreezeArgs<R> a) {
   const int grp = (a.groups > 1) ? tid / a.n_out : 0;
   const int o0 = (a.groups > 1) ? tid % a.n_out : tid;
   const bool active = grp < a.groups;
-  double acc[kFoOutPerLane], cph[kFoOutPerLane], sph[kFoOutPerLane], ptv[kFoOutPerLane];
-  int row[kFoOutPerLane];
-  bool own[kFoOutPerLane];
+  double acc[OPL], cph[OPL], sph[OPL], ptv[OPL];
+  int row[OPL];
+  bool own[OPL];
 #pragma unroll
-  for (int m = 0; m < kFoOutPerLane; ++m) {
+  for (int m = 0; m < OPL; ++m) {
     const int o = o0 + m * per;
     own[m] = active && (a.groups > 1 ? m == 0 : o < a.n_out);
     const int k = own[m] ? o % a.n_phi : 0;
@@ -91,7 +93,7 @@ __global__ void __launch_bounds__(kFoThreads) k_fo_partial(FreezeArgs<R> a) {
       for (int c = grp; c < ncell; c += a.groups) {
         const double cw = s_w[c], cvx = s_vx[c], cvy = s_vy[c], cgt = s_gt[c], cwp = s_wp[c];
 #pragma unroll
-        for (int m = 0; m < kFoOutPerLane; ++m) {
+        for (int m = 0; m < OPL; ++m) {
           if (!own[m]) continue;
           const double D = fma(-cvy, sph[m], fma(-cvx, cph[m], 1.0));
           if (row[m] == 0) {
@@ -117,7 +119,7 @@ __global__ void __launch_bounds__(kFoThreads) k_fo_partial(FreezeArgs<R> a) {
     }
   } else {
 #pragma unroll
-    for (int m = 0; m < kFoOutPerLane; ++m)
+    for (int m = 0; m < OPL; ++m)
       if (own[m]) out[o0 + m * per] = acc[m];
   }
 }
@@ -161,7 +163,11 @@ __global__ void __launch_bounds__(64) k_fo_harm(const double* spectra, int n_phi
 
 template <class R>
 hipError_t launch_freezeout(const FreezeArgs<R>& a, double* spectra, double* harm, int n_harm, hipStream_t st) {
-  hipLaunchKernelGGL((k_fo_partial<R>), dim3(kFoBlocks), dim3(kFoThreads), 0, st, a);
+  static_assert(kFoOutPerLane == 4, "outputs per lane: 1, 2 or 4");
+  const int opl = (a.n_out + kFoThreads - 1) / kFoThreads;
+  if (opl <= 1) hipLaunchKernelGGL((k_fo_partial<R, 1>), dim3(kFoBlocks), dim3(kFoThreads), 0, st, a);
+  else if (opl == 2) hipLaunchKernelGGL((k_fo_partial<R, 2>), dim3(kFoBlocks), dim3(kFoThreads), 0, st, a);
+  else hipLaunchKernelGGL((k_fo_partial<R, 4>), dim3(kFoBlocks), dim3(kFoThreads), 0, st, a);
   hipLaunchKernelGGL(k_fo_final, dim3((a.n_out + 255) / 256), dim3(256), 0, st, a.part, kFoBlocks, a.n_out, spectra);
   if (harm) hipLaunchKernelGGL(k_fo_harm, dim3(a.rows), dim3(64), 0, st, spectra, a.n_phi, n_harm, harm);
   return hipGetLastError();

@@ -157,6 +157,7 @@ struct BatchArgs {
   int stage;              // 1..3; 0: L written to U1 (no state change)
   R eps;
   int xtb;                // workgroup size of the x-row launch (rows per item: xtb / nx)
+  int tile_a;             // 31 or 32: every event's tile length along the launched axis (0: they differ)
   long long xlds;         // its dynamic LDS bytes (the largest event)
 };
 

@@ -1004,6 +1004,43 @@ __global__ void __launch_bounds__(512) k_btile(BatchArgs<R> b) {
   }
 }
 
+// The same when every event has the tile length A along the axis (the
+// launcher checks): one tile body instead of two, so the y/z faces are taken
+// in pairs as in the single-event kernels (same bits either way).  PERSIST:
+// workgroups walk items blockIdx.x, blockIdx.x + gridDim.x, ...; otherwise
+// one item per workgroup (the loop's live state costs ~20 VGPRs, a
+// workgroup per CU).
+template <class R, int S, int AX, int A>
+__device__ __forceinline__ void btile_item(const BatchArgs<R>& b, long long it, R* s) {
+  const int e = batch_event_of(b.off, b.n_events, it);
+  const BatchEvent& ev = b.ev[e];
+  const long long local = it - b.off[e];
+  const StageArgs<R> a = batch_stage_args<R>(ev, b.stage, b.eps, AX);
+  if (AX == 0) {
+    const int gx = (ev.g.n[0] + A - 1) / A, gy = (ev.g.n[1] + kXTileY - 1) / kXTileY;
+    const int bx = (int)(local % gx), by = (int)((local / gx) % gy), bz = (int)(local / ((long long)gx * gy));
+    xtile_body<R, S, A>(a, bx, by, bz, s);
+  } else {
+    const int gx = (ev.g.n[0] + kTileX - 1) / kTileX, ga = (ev.g.n[AX] + A - 1) / A;
+    const int bx = (int)(local % gx), by = (int)((local / gx) % ga), bz = (int)(local / ((long long)gx * ga));
+    tile_body<R, S, AX, AX == 2, A, true>(a, bx, by, bz, s);
+  }
+}
+
+template <class R, int S, int AX, int A, bool PERSIST>
+__global__ void __launch_bounds__(512) k_btile_u(BatchArgs<R> b) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  R* s = reinterpret_cast<R*>(smem_raw);
+  if constexpr (PERSIST) {
+    for (long long it = blockIdx.x; it < b.items; it += gridDim.x) {
+      btile_item<R, S, AX, A>(b, it, s);
+      __syncthreads();  // the next item overwrites the LDS tile
+    }
+  } else {
+    if ((long long)blockIdx.x < b.items) btile_item<R, S, AX, A>(b, blockIdx.x, s);  // uniform
+  }
+}
+
 // x rows of every event: items are groups of TB / nx rows (xrows_body).
 template <class R, int S, int TB>
 __global__ void __launch_bounds__(TB) k_bxrows(BatchArgs<R> b) {
@@ -1219,6 +1256,19 @@ long long batch_items(int AX, const Grid& g, int xtb, int elem) {
 }
 
 // blocks: workgroups of the launch (0: one per item).
+template <class R, int S>
+void launch_btile_u(int AX, int A, bool persist, dim3 grid, const BatchArgs<R>& b, hipStream_t st) {
+  const size_t lds = (size_t)2 * 5 * (A + 8) * 16 * sizeof(R);
+  const dim3 tb(512);
+#define HYDRO_BTU(AXV, AV)                                                                 \
+  if (AX == AXV && A == AV) {                                                              \
+    if (persist) hipLaunchKernelGGL((k_btile_u<R, S, AXV, AV, true>), grid, tb, lds, st, b);  \
+    else hipLaunchKernelGGL((k_btile_u<R, S, AXV, AV, false>), grid, tb, lds, st, b);          \
+  }
+  HYDRO_BTU(0, 31) HYDRO_BTU(1, 31) HYDRO_BTU(2, 31) HYDRO_BTU(0, 32) HYDRO_BTU(1, 32) HYDRO_BTU(2, 32)
+#undef HYDRO_BTU
+}
+
 template <class R>
 hipError_t launch_batch_axis(int AX, const BatchArgs<R>& b, int scheme, long long blocks, hipStream_t st) {
   const long long nb = (blocks <= 0 || blocks > b.items) ? b.items : blocks;
@@ -1226,6 +1276,9 @@ hipError_t launch_batch_axis(int AX, const BatchArgs<R>& b, int scheme, long lon
   const size_t lds = (size_t)2 * 5 * (32 + 8) * 16 * sizeof(R);  // the largest y/z tile (A = 32)
   const dim3 grid((unsigned)nb), tb(512);
   const size_t xl = (size_t)b.xlds;
+  // the uniform-tile-length kernels for plain WENO faces and WENO7-Z with the
+  // limiter (the other limited schemes and MUSTA-FORCE keep the general one)
+  const bool uni = (scheme & (kPP | kMusta)) == 0 || scheme == (kWenoZ | kPP);
 #define HYDRO_BAXIS(S)                                                                                      \
   if (AX == 3) {                                                                                            \
     switch (b.xtb) {                                                                                        \
@@ -1236,6 +1289,9 @@ hipError_t launch_batch_axis(int AX, const BatchArgs<R>& b, int scheme, long lon
     }                                                                                                       \
   } else if (AX == 4) {                                                                                     \
     hipLaunchKernelGGL((k_bxbound<R, S>), grid, dim3(kXBoundRows * 10), 0, st, b);                          \
+  } else if (uni && (b.tile_a == 31 || b.tile_a == 32)) {                                                  \
+    if ((S & kPP) != 0) launch_btile_u<R, (kWenoZ | kPP)>(AX, b.tile_a, nb < b.items, grid, b, st);         \
+    else launch_btile_u<R, (S & 7)>(AX, b.tile_a, nb < b.items, grid, b, st);                                \
   } else if (AX == 0) {                                                                                     \
     hipLaunchKernelGGL((k_btile<R, S, 0>), grid, tb, lds, st, b);                                          \
   } else if (AX == 1) {                                                                                     \
