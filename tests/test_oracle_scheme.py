@@ -166,6 +166,39 @@ def test_jet_outside_box_or_not_started_deposits_nothing():
         assert P[0] == 0.0 and np.all(L == 0.0)
 
 
+def test_jet_depletion_stops_the_deposit():
+    """A jet with little energy in a hot medium (periodic, so that the box's
+    energy changes only by the source): each step removes from the jet
+    exactly what the ledger gains and the box's total energy gains (Eq. 2's
+    source is the jet's loss); the step that would take the jet below zero
+    still deposits in full (the jet was alive at its start) and leaves E_jet
+    = 0; after it nothing is deposited and the state keeps its energy."""
+    n = (12, 12, 12)
+    pb = small_problem(n, bc="periodic")
+    U = O.prim_to_cons(pb, W.uniform_prim(n, e=30.0, v=(0.1, 0.0, 0.0)))
+    jet = O.Jet(x0=(0.013, 0.021, -0.017), E0=0.2)
+    dV = 1e-3
+    st = O.RunState(U=U, Ejet=np.array([jet.E0]))
+    E_prev, led_prev, depleted_at = float(st.U[0].sum() * dV), 0.0, None
+    for k in range(8):
+        Ej_prev = float(st.Ejet[0])
+        st = O.run(pb, st.U, 1, [jet], step0=k, Ejet=st.Ejet, ledger=st.ledger)
+        E_now = float(st.U[0].sum() * dV)
+        gain = st.ledger - led_prev
+        assert E_now - E_prev == pytest.approx(gain, rel=1e-9, abs=1e-13)
+        if depleted_at is None:
+            assert gain > 0
+            if st.Ejet[0] == 0.0:
+                depleted_at = k
+                assert gain >= Ej_prev
+            else:
+                assert Ej_prev - st.Ejet[0] == pytest.approx(gain, rel=1e-12)
+        else:
+            assert gain == 0.0 and st.Ejet[0] == 0.0
+        E_prev, led_prev = E_now, st.ledger
+    assert depleted_at is not None and depleted_at < 7
+
+
 def test_ngp_tie_goes_to_upper_cell():
     # x = 0 lies on the face between cells 3 and 4 of an 8-cell axis.
     n = (8, 8, 8)
