@@ -83,9 +83,15 @@ PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3}  # MI355X vector FP64 / FP32 (packed)
 # kernel sources with the given hash (KERNEL_SOURCES); reported as null once
 # any of them changes.  Source: profiles/stage_256cube_f64.md.
 MEASURED_TRAFFIC = {
-    ("zmarch", "f64", "tile", 256): {"kernels_sha256": "4090c4d1e3989375",
-                                     "read_bytes": 897328 * 2.0 * 1024, "write_bytes": 655360 * 1.0 * 1024},
+    ("zmarch", "f64", "tile", 256, 2): {"kernels_sha256": "41591a538f915de9",
+                                        "read_bytes": 956077 * 2.0 * 1024, "write_bytes": 655360 * 1.0 * 1024},
 }
+# The whole stage from the same counters, in fields (one field = one full
+# read or write of one of the five state fields) per cell and stage: x faces
+# 5 + 5, outflow x faces 0.63 + 0.08, y tiles 10 + 5, z tiles 14.59 + 5, the
+# per-step sums 5 / 3; the minimal stage moves 13.33 (10 / 15 / 15).
+MEASURED_STAGE_FIELDS = {("f64", "tile", 256, 2): {"kernels_sha256": "41591a538f915de9",
+                                                   "fields": 10.0 + 0.71 + 15.0 + 19.59 + 5.0 / 3}}
 KERNEL_SOURCES = ("hydro_kernels.hip", "hydro_device.hpp", "hydro_internal.hpp")
 
 
@@ -420,10 +426,17 @@ def main():
     achieved = fpc[dom] * nc / (t_launch * 1e-3) / 1e12
     peak = PEAK_TFLOPS[args.precision]
     traffic = None
-    rec = (MEASURED_TRAFFIC.get((dom, args.precision, args.yz, args.n))
+    rec = (MEASURED_TRAFFIC.get((dom, args.precision, args.yz, args.n, args.tile_order))
            if args.weno == "z" and args.limiter == "none" and args.flux == "weno" else None)
     if rec is not None and kernels_sha256() == rec["kernels_sha256"]:
         traffic = rec["read_bytes"] + rec["write_bytes"]
+    srec = (MEASURED_STAGE_FIELDS.get((args.precision, args.yz, args.n, args.tile_order))
+            if args.weno == "z" and args.limiter == "none" and args.flux == "weno" else None)
+    stage_traffic = None
+    if srec is not None and kernels_sha256() == srec["kernels_sha256"]:
+        stage_traffic = {"fields_per_cell_stage": srec["fields"], "algorithmic_fields": 40.0 / 3,
+                         "ratio": srec["fields"] / (40.0 / 3),
+                         "bytes_per_stage": srec["fields"] * nc * (8 if args.precision == "f64" else 4)}
     roofline = {"bound": "alu", "kernel": dom, "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
                 "frac": achieved / peak, "traffic": traffic,
                 "algorithmic_bytes": BYTES_PER_CELL[dom] * (8 if args.precision == "f64" else 4) * nc,
@@ -456,6 +469,7 @@ def main():
                    "musta_k": args.musta_k if args.flux == "musta" else None},
         "roofline": roofline,
         "step_alu_frac": step_frac,
+        "stage_traffic": stage_traffic,
         "flops_per_cell_update": fpc_update,
         "kernels": per_kernel,
         "fixups": fix,

@@ -1051,7 +1051,7 @@ __global__ void __launch_bounds__(TB) k_bxrows(BatchArgs<R> b) {
     const BatchEvent& ev = b.ev[e];
     const int rpi = xrow_rows(ev.g.n[0], TB, (int)sizeof(R));
     const StageArgs<R> a = batch_stage_args<R>(ev, b.stage, b.eps, 0);
-    xrows_body<R, S, false>(a, (it - b.off[e]) * rpi, rpi, s);
+    xrows_body<R, S, sizeof(R) == 4>(a, (it - b.off[e]) * rpi, rpi, s);  // FP64 pairs cost 18 VGPRs here
     __syncthreads();  // the next item overwrites the LDS rows
   }
 }
