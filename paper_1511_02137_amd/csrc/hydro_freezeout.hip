@@ -40,8 +40,10 @@ __global__ void __launch_bounds__(kFoThreads) k_fo_partial(FreezeArgs<R> a) {
   __shared__ double s_w[kFoThreads], s_vx[kFoThreads], s_vy[kFoThreads], s_gt[kFoThreads], s_wp[kFoThreads];
   __shared__ double s_red[kFoThreads];
   const int tid = threadIdx.x;
-  // outputs of this lane: o = tid % per_group + m * kFoThreads / groups ... (groups == 1 when n_out > 256)
-  const int per = (a.groups > 1) ? a.n_out : kFoThreads;  // outputs spanned by one group
+  // Outputs of this lane.  groups > 1 (n_out <= 128): lane tid is in group
+  // tid / n_out and owns output tid % n_out; the groups split the chunk's
+  // cells.  groups == 1: lane tid owns outputs tid + 256 m, m < OPL.
+  const int per = (a.groups > 1) ? a.n_out : kFoThreads;  // stride between a lane's outputs
   const int grp = (a.groups > 1) ? tid / a.n_out : 0;
   const int o0 = (a.groups > 1) ? tid % a.n_out : tid;
   const bool active = grp < a.groups;
@@ -91,7 +93,9 @@ __global__ void __launch_bounds__(kFoThreads) k_fo_partial(FreezeArgs<R> a) {
     const int ncell = (int)min((long long)kFoThreads, a.nc - ch * kFoThreads);
     if (active) {
       for (int c = grp; c < ncell; c += a.groups) {
-        const double cw = s_w[c], cvx = s_vx[c], cvy = s_vy[c], cgt = s_gt[c], cwp = s_wp[c];
+        const double cwp = s_wp[c];
+        if (cwp == 0.0) continue;  // below T_min (or past the grid): contributes nothing
+        const double cw = s_w[c], cvx = s_vx[c], cvy = s_vy[c], cgt = s_gt[c];
 #pragma unroll
         for (int m = 0; m < OPL; ++m) {
           if (!own[m]) continue;
