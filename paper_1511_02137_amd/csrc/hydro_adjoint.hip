@@ -92,7 +92,7 @@ __device__ __forceinline__ PrimJ c2p_jac_known(double E, double Mx, double My, d
   const double M[3] = {Mx, My, Mz};
   const double s = E + e;
   const double W = E + e * (1.0 / 3.0);
-  const double inv = 1.0 / (s * W);
+  const double inv = rcp_nr(s * W);
   const double is = W * inv;
   J.e = e;
   J.iW = s * inv;
@@ -155,7 +155,7 @@ __device__ __forceinline__ void split_flux_vjp(const R u[5], const PrimJ& J, con
   double vb[3] = {0.0, 0.0, 0.0};
   vb[AX] = vbd;
   double Eb, Mb[3];
-  c2p_vjp(J, pb / 3.0, vb, Eb, Mb);
+  c2p_vjp(J, pb * (1.0 / 3.0), vb, Eb, Mb);
   ub[0] += Eb;
   for (int k = 0; k < 3; ++k) ub[1 + k] += Mb[k];
 }
@@ -191,12 +191,16 @@ __device__ __forceinline__ void weno7_vjp(const R* a, R phi, R eps, R* ab) {
     const R hk[4] = {R(2.5), R(1.5), R(0.5), R(-0.5)};
     const R mk[4] = {R(11.0 / 6.0), R(1.0 / 3.0), R(-1.0 / 6.0), R(1.0 / 3.0)};
     const R gk[4] = {R(2), R(1), R(0), R(-1)};
-    R b[4], sk[4], ck[4];
+    // X_k = 13/12 c_k and Y_k = 781/720 D3_k are kept: half the indicator's
+    // partials in c_k and D3_k
+    R b[4], sk[4], ck[4], X[4], Y[4];
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
       sk[k] = fma(mk[k], g[k], fma(hk[k], f[k], e[k]));
       ck[k] = fma(gk[k], g[k], f[k]);
-      b[k] = fma(sk[k], sk[k], fma(R(13.0 / 12.0) * ck[k], ck[k], fma(R(781.0 / 720.0) * g[k], g[k], eps)));
+      X[k] = R(13.0 / 12.0) * ck[k];
+      Y[k] = R(781.0 / 720.0) * g[k];
+      b[k] = fma(sk[k], sk[k], fma(X[k], ck[k], fma(Y[k], g[k], eps)));
     }
     R iv[4];
     if (sizeof(R) == 8) {
@@ -212,11 +216,10 @@ __device__ __forceinline__ void weno7_vjp(const R* a, R phi, R eps, R* ab) {
       for (int k = 0; k < 4; ++k) iv[k] = rcp_approx<R>(b[k]);
     }
     R w[4], s[4];
-    R sg = R(1);
+    R traw = R(0);
     if (S == kWenoZ) {
-      const R traw = fma(R(3), b[1] - b[2], b[0] - b[3]);
-      sg = traw < R(0) ? R(-1) : R(1);
-      const R tau = sg * traw;
+      traw = fma(R(3), b[1] - b[2], b[0] - b[3]);
+      const R tau = fabs(traw);
 #pragma unroll
       for (int k = 0; k < 4; ++k) {
         s[k] = tau * iv[k];
@@ -237,33 +240,39 @@ __device__ __forceinline__ void weno7_vjp(const R* a, R phi, R eps, R* ab) {
     rb2 = pin * w[2];
     rb3 = pin * w[3];
     const R rr[4] = {r0, r1, r2, r3};
-    R bb[4];
-    R taub = R(0);
+    // bb2[k] = 2 dR/db_k, formed directly (4 dR/dw_k below): the factor 2 of
+    // every partial of b_k = s_k^2 + X_k c_k + Y_k D3_k + eps then needs no
+    // multiply (powers of two scale exactly, so this is bit-identical to
+    // forming dR/db_k and doubling it)
+    const R pin4 = R(4) * pin;
+    R bb2[4];
+    R taub2 = R(0);  // 2 dR/dtau
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-      const R wb = pin * fma(-dk[k], corr, rr[k]);  // dR/dw_k
+      const R wb4 = pin4 * fma(-dk[k], corr, rr[k]);  // 4 dR/dw_k
       if (S == kWenoZ) {
-        const R t = (wb + wb) * (s[k] * iv[k]);      // dR/dtau through w_k
-        bb[k] = -t * s[k];
-        taub = taub + t;
+        const R t2 = wb4 * (s[k] * iv[k]);  // 2 dR/dtau through w_k
+        bb2[k] = -t2 * s[k];
+        taub2 = taub2 + t2;
       } else {
-        bb[k] = R(-2) * wb * (w[k] * iv[k]);
+        bb2[k] = -wb4 * (w[k] * iv[k]);
       }
     }
     if (S == kWenoZ) {
-      const R t = sg * taub;
-      bb[0] = bb[0] + t;
-      bb[1] = fma(R(3), t, bb[1]);
-      bb[2] = fma(R(-3), t, bb[2]);
-      bb[3] = bb[3] - t;
+      const R t = traw < R(0) ? -taub2 : taub2;  // tau = |traw|
+      bb2[0] = bb2[0] + t;
+      bb2[1] = fma(R(3), t, bb2[1]);
+      bb2[2] = fma(R(-3), t, bb2[2]);
+      bb2[3] = bb2[3] - t;
     }
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-      const R sb = R(2) * sk[k] * bb[k];
-      const R cb = R(13.0 / 6.0) * ck[k] * bb[k];
+      const R sb = sk[k] * bb2[k];  // s_k partial
+      const R cb = X[k] * bb2[k];   // c_k partial
+      const R gd = Y[k] * bb2[k];   // D3_k partial (direct term)
       eb[k] = sb;
       fb[k] = fma(hk[k], sb, cb);
-      gb[k] = fma(mk[k], sb, fma(gk[k], cb, R(781.0 / 360.0) * g[k] * bb[k]));
+      gb[k] = (k == 2) ? fma(mk[k], sb, gd) : fma(mk[k], sb, fma(gk[k], cb, gd));  // g_2 = 0
     }
     eb[4] = R(0);
     eb[5] = R(0);
@@ -347,30 +356,26 @@ __global__ void __launch_bounds__(TBMAX) k_line_adj(AdjArgs<R> a) {
   const int TB = blockDim.x;
   unsigned fix = 0;
 
-  // points: lane handles t = tid and t = tid + TB (slot j = padded index + 4)
-  int slot[2] = {-1, -1};
-  R uo[2][5];
-  double eo[2] = {0.0, 0.0};     // recovered e of the point
-  bool fixed[2] = {false, false};  // the recovery fixed the point up
+  // Points: lane tid < n recomputes the split fluxes of its own cell (slot
+  // tid + 4).  A ghost point (slots 0..3, n+4..n+7) is a copy of the cell it
+  // maps to, so its split fluxes are copied in LDS, and in the reverse its
+  // split-flux adjoints are added to that cell's before the one split-flux
+  // VJP (the same Jacobian, so this equals reversing the ghost on its own).
+  R uo[5];
+  double eo = 0.0;     // recovered e of the own cell
+  bool fixed = false;  // the recovery fixed the own cell up
+  if (tid < n) {
+    load5(a.W, nc, base + (long long)tid * stride, uo);
+    const unsigned f0 = fix;
+    const PrimV pv = c2p(uo, fix);
+    eo = pv.e;
+    fixed = fix != f0;
+    R Fp[5], Fm[5];
+    split_flux<R, AX>(uo, pv, Fp, Fm);
 #pragma unroll
-  for (int q = 0; q < 2; ++q) {
-    const int t = tid + q * TB;
-    if (t < n + 8) {
-      const int j = (t < n) ? t + 4 : (t < n + 4 ? t - n : t);
-      slot[q] = j;
-      const int src = map_idx(j - 4, n, bc);
-      load5(a.W, nc, base + (long long)src * stride, uo[q]);
-      const unsigned f0 = fix;
-      const PrimV pv = c2p(uo[q], fix);
-      eo[q] = pv.e;
-      fixed[q] = fix != f0;
-      R Fp[5], Fm[5];
-      split_flux<R, AX>(uo[q], pv, Fp, Fm);
-#pragma unroll
-      for (int c = 0; c < 5; ++c) {
-        sFp[c * P + j] = Fp[c];
-        sFm[c * P + j] = Fm[c];
-      }
+    for (int c = 0; c < 5; ++c) {
+      sFp[c * P + tid + 4] = Fp[c];
+      sFm[c * P + tid + 4] = Fm[c];
     }
   }
   R my[5];  // mu of the lane's own cell (used by the fused combine)
@@ -382,6 +387,16 @@ __global__ void __launch_bounds__(TBMAX) k_line_adj(AdjArgs<R> a) {
     }
   }
   __syncthreads();
+  // ghost slot of lane tid < 8: slot jg, copy of cell map_idx(jg - 4)
+  const int jg = tid < 4 ? tid : n + tid;
+  if (tid < 8) {
+    const int src = map_idx(jg - 4, n, bc) + 4;
+#pragma unroll
+    for (int c = 0; c < 5; ++c) {
+      sFp[c * P + jg] = sFp[c * P + src];
+      sFm[c * P + jg] = sFm[c * P + src];
+    }
+  }
   // face adjoints phi(x - 1/2) = (mu(x) - mu(x-1)) / dx
   R phi[5];
   if (tid < n) {
@@ -397,12 +412,21 @@ __global__ void __launch_bounds__(TBMAX) k_line_adj(AdjArgs<R> a) {
     sX[row * Q + (k < 8 ? k : n + k)] = R(0);
   }
 
-  R acc[2][2][5];  // [point][split][field]
+  // slot j is argument m of face j - m (F+) and of face j - 7 + m (F-)
+  auto gather = [&](int j, R& sp, R& sm) {
+    sp = R(0);
+    sm = R(0);
+#pragma unroll
+    for (int m = 0; m < 7; ++m) {
+      sp = sp + sX[m * Q + j - m + 8];
+      sm = sm + sX[(7 + m) * Q + j - 7 + m + 8];
+    }
+  };
+  R acc[2][5];  // [split][field] of the own cell
 #pragma unroll
   for (int c = 0; c < 5; ++c) {
     if (c == 4 && a.skip_n) {  // uniform over the workgroup
-#pragma unroll
-      for (int q = 0; q < 2; ++q) acc[q][0][c] = acc[q][1][c] = R(0);
+      acc[0][c] = acc[1][c] = R(0);
       continue;
     }
     if (tid < n) {
@@ -419,62 +443,47 @@ __global__ void __launch_bounds__(TBMAX) k_line_adj(AdjArgs<R> a) {
       for (int m = 0; m < 7; ++m) sX[(7 + m) * Q + tid + 8] = ab[m];
     }
     __syncthreads();
-#pragma unroll
-    for (int q = 0; q < 2; ++q) {
-      const int j = slot[q];
-      R sp = R(0), sm = R(0);
-      if (j >= 0) {
-        // slot j is argument m of face j - m (F+) and of face j - 7 + m (F-)
-#pragma unroll
-        for (int m = 0; m < 7; ++m) {
-          sp = sp + sX[m * Q + j - m + 8];
-          sm = sm + sX[(7 + m) * Q + j - 7 + m + 8];
-        }
-      }
-      acc[q][0][c] = sp;
-      acc[q][1][c] = sm;
+    if (tid < n) gather(tid + 4, acc[0][c], acc[1][c]);
+    if (tid < 8) {
+      // the ghost's sums go to slots 0..7 of field c's rows, which no lane
+      // reads again (field c's reconstructions are done)
+      R gp, gm;
+      gather(jg, gp, gm);
+      sFp[c * P + tid] = gp;
+      sFm[c * P + tid] = gm;
     }
     __syncthreads();
   }
 
-  // split-flux adjoint -> adjoint of W at the point; own cells to LDS, ghosts after
-  R* sW = s;            // [5][n]   (reuses sFp)
-  R* sGh = s + 5 * n;   // [5][8]
+  if (tid < n) {
+    // ghosts in slot order onto the cells they copy
 #pragma unroll
-  for (int q = 0; q < 2; ++q) {
-    const int j = slot[q];
-    if (j < 0) continue;
-    const double E = (double)uo[q][0], Mx = (double)uo[q][1], My = (double)uo[q][2], Mz = (double)uo[q][3];
-    const PrimJ J = fixed[q] ? c2p_jac(E, Mx, My, Mz) : c2p_jac_known(E, Mx, My, Mz, eo[q]);
+    for (int g = 0; g < 8; ++g) {
+      const int j = g < 4 ? g : n + g;
+      if (map_idx(j - 4, n, bc) == tid) {
+#pragma unroll
+        for (int c = 0; c < 5; ++c) {
+          if (c == 4 && a.skip_n) continue;  // slots still hold field 4's split fluxes
+          acc[0][c] = acc[0][c] + sFp[c * P + g];
+          acc[1][c] = acc[1][c] + sFm[c * P + g];
+        }
+      }
+    }
+    // split-flux adjoint -> adjoint of W at the cell
+    const double E = (double)uo[0], Mx = (double)uo[1], My = (double)uo[2], Mz = (double)uo[3];
+    const PrimJ J = fixed ? c2p_jac(E, Mx, My, Mz) : c2p_jac_known(E, Mx, My, Mz, eo);
     double ap[5], am[5], ub[5];
 #pragma unroll
     for (int c = 0; c < 5; ++c) {
-      ap[c] = (double)acc[q][0][c];
-      am[c] = (double)acc[q][1][c];
+      ap[c] = (double)acc[0][c];
+      am[c] = (double)acc[1][c];
     }
-    split_flux_vjp<R, AX>(uo[q], J, ap, am, ub);
-    if (j >= 4 && j < n + 4) {
-      for (int c = 0; c < 5; ++c) sW[c * n + j - 4] = (R)ub[c];
-    } else {
-      const int gslot = j < 4 ? j : j - n;  // 0..7
-      for (int c = 0; c < 5; ++c) sGh[c * 8 + gslot] = (R)ub[c];
-    }
-  }
-  __syncthreads();
-  if (tid == 0) {
-    for (int gslot = 0; gslot < 8; ++gslot) {
-      const int j = gslot < 4 ? gslot : gslot + n;
-      const int cell = map_idx(j - 4, n, bc);
-      for (int c = 0; c < 5; ++c) sW[c * n + cell] = sW[c * n + cell] + sGh[c * 8 + gslot];
-    }
-  }
-  __syncthreads();
-  if (tid < n) {
+    split_flux_vjp<R, AX>(uo, J, ap, am, ub);
     const long long cell = base + (long long)tid * stride;
 #pragma unroll
     for (int c = 0; c < 5; ++c) {
       const long long q = c * nc + cell;
-      const R gv = a.first ? sW[c * n + tid] : a.G[q] + sW[c * n + tid];
+      const R gv = a.first ? (R)ub[c] : a.G[q] + (R)ub[c];
       if (a.stage == 0) {
         a.G[q] = gv;
       } else {

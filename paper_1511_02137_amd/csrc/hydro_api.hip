@@ -332,8 +332,9 @@ int adjoint_impl(hydro_ctx* ctx, const R* Uc, int64_t step0, const double* E0, i
     HYDRO_TRY(launch_copy_f64(ctx->dev->E_jet, ctx->Ehist + (size_t)i * kMaxJets, kMaxJets, st));
     HYDRO_TRY(stage_impl<R>(ctx, st_ptr(i, 0), st_ptr(i, 0), st_ptr(i, 1), 1, tn, st));
     HYDRO_TRY(stage_impl<R>(ctx, st_ptr(i, 1), st_ptr(i, 0), st_ptr(i, 2), 2, tn + dt, st));
-    R* out = (i + 1 < K) ? st_ptr(i + 1, 0) : static_cast<R*>(ctx->U1);
-    HYDRO_TRY(stage_impl<R>(ctx, st_ptr(i, 2), st_ptr(i, 0), out, 3, tn + 0.5 * dt, st));
+    // the segment's last output is the next checkpoint, which the reverse
+    // sweep does not read (the jet energies are restored below)
+    if (i + 1 < K) HYDRO_TRY(stage_impl<R>(ctx, st_ptr(i, 2), st_ptr(i, 0), st_ptr(i + 1, 0), 3, tn + 0.5 * dt, st));
   }
   // reverse sweep
   AdjArgs<R> a;
