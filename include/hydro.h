@@ -318,9 +318,14 @@ typedef enum {
   HYDRO_OPT_MARCH_SEG = 1,  /* cells per march segment (default 32) */
   HYDRO_OPT_X_KERNEL = 2,   /* x faces: 0 = one row per workgroup (default), 1 = 32 x 16 LDS tiles */
   HYDRO_OPT_ADJ_SKIP_N = 3, /* 0 (default) or 1, see above */
-  HYDRO_OPT_TILE_ORDER = 4  /* order of the y/z LDS tiles' workgroups, 0..3: bit 0 (y tiles), bit 1 (z
+  HYDRO_OPT_TILE_ORDER = 4, /* order of the y/z LDS tiles' workgroups, 0..3: bit 0 (y tiles), bit 1 (z
                                tiles) set = neighbouring workgroups share the tile index and step the
                                transverse axis, clear = they step along the axis; default 2 */
+  HYDRO_OPT_ADJ_LINES = 5   /* lines per workgroup of the y and z line adjoints: 0 = automatic
+                               (default, 2), 1, 2 or 4; fewer where n_x is not a multiple or the
+                               workgroup would exceed 1024 lanes or 64 KiB of LDS.  Neighbouring x
+                               lines share the workgroup, so their strided loads share cache lines;
+                               every line is computed by the same arithmetic (same results) */
 } hydro_option;
 
 /* Set / read an option; HYDRO_EINVAL for an unknown option or bad value. */

@@ -335,13 +335,19 @@ __device__ __forceinline__ long long xcd_line(long long nlines) {
   return (long long)(blockIdx.x % 8) * per + blockIdx.x / 8;
 }
 
-template <class R, int S, int AX, int TBMAX>
+template <class R, int S, int AX, int TBMAX, int NL>
 __global__ void __launch_bounds__(TBMAX) k_line_adj(AdjArgs<R> a) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  R* s = reinterpret_cast<R*>(smem_raw);
   const long long nlines = n_lines(AX, a.g);
-  const long long L = xcd_line(nlines);
-  if (L >= nlines) return;  // whole workgroup
+  // NL neighbouring lines (consecutive x) per workgroup, lanes interleaved
+  // line-fastest, so that the strided loads and stores of y and z lines
+  // fetch NL neighbouring values per cache line; each line has its own LDS
+  // area (pitch chosen so that the lines' copies fall in different banks)
+  const long long ngroups = nlines / NL;
+  const long long grp = xcd_line(ngroups);
+  if (grp >= ngroups) return;  // whole workgroup
+  const int xi = threadIdx.x % NL;
+  const long long L = grp * NL + xi;
   const int n = a.g.n[AX];
   const int bc = a.g.bc[AX];
   const int P = n + 8;
@@ -349,11 +355,12 @@ __global__ void __launch_bounds__(TBMAX) k_line_adj(AdjArgs<R> a) {
   const long long nc = a.g.nc;
   long long stride;
   const long long base = line_base(AX, L, a.g, stride);
+  R* s = reinterpret_cast<R*>(smem_raw) + (long long)xi * line_adj_pitch(n, NL);
   R* sFp = s;               // [5][P]
   R* sFm = s + 5 * P;       // [5][P]
   R* sX = s + 10 * P;       // [2][7][Q]; first used to stage mu [5][n]
-  const int tid = threadIdx.x;
-  const int TB = blockDim.x;
+  const int tid = threadIdx.x / NL;  // point / face of the lane in its line
+  const int TB = blockDim.x / NL;    // lanes per line
   unsigned fix = 0;
 
   // Points: lane tid < n recomputes the split fluxes of its own cell (slot
@@ -503,62 +510,86 @@ __global__ void __launch_bounds__(TBMAX) k_line_adj(AdjArgs<R> a) {
   add_fixups(a.fixups, fix);
 }
 
-// Outflow face n-1/2 of every line along AX: phi = -mu(n-1)/dx.  A
-// workgroup takes 32 lines: (1) one lane per stencil point computes the split
-// fluxes of the eight points n-4..n+3 (ghosts copy cell n-1); (2) one lane per
-// (line, field, split) reverses that reconstruction; (3) one lane per point
-// reverses the split; (4) one lane per (line, field) adds the eight points'
-// adjoints to their cells in a fixed order.
+// Outflow face n-1/2 of every line along AX: phi = -mu(n-1)/dx.  Its
+// stencil points n-4..n+3 are the cells clamp(n-4+m) (the ghosts copy cell
+// n-1), so they fall into runs of equal cells; the first point of a run
+// stands for it.  A workgroup takes 32 lines: (1) one lane per run recovers
+// its cell and forms the split fluxes; (2) one lane per (line, field, split)
+// reverses that reconstruction; (3) the lane of each run adds the run's
+// reconstruction adjoints in point order, reverses the split through the
+// cell's Jacobian and adds the result to G (distinct cells, so no two lanes
+// touch the same element).
 constexpr int kBoundLines = 32;
+
+__device__ __forceinline__ int bound_cell(int n, int m) { return min(max(n - 4 + m, 0), n - 1); }
+// first point of m's run of equal cells
+__device__ __forceinline__ int bound_rep(int n, int m) {
+  const int k = bound_cell(n, m);
+  return k == 0 ? 0 : k - (n - 4);
+}
 
 template <class R, int S, int AX>
 __global__ void __launch_bounds__(kBoundLines * 10) k_bound_adj(AdjArgs<R> a) {
-  __shared__ R sF[kBoundLines][8][10];        // split fluxes (F+ 0..4, F- 5..9); later the W adjoints [.][.][5]
+  __shared__ R sF[kBoundLines][4][10];        // split fluxes of the runs' cells (F+ 0..4, F- 5..9)
   __shared__ double sA[kBoundLines][8][10];   // reconstruction adjoints per point
   const long long nlines = n_lines(AX, a.g);
   const int n = a.g.n[AX];
   const long long nc = a.g.nc;
   const int tid = threadIdx.x;
   unsigned fix = 0;
-  // (1) split fluxes, lane = (line, point)
-  if (tid < kBoundLines * 8) {
-    const int l = tid >> 3, m = tid & 7;
-    const long long L = (long long)blockIdx.x * kBoundLines + l;
-    if (L < nlines) {
-      long long stride;
-      const long long base = line_base(AX, L, a.g, stride);
-      R u[5];
-      load5(a.W, nc, base + (long long)map_idx(n - 4 + m, n, 0) * stride, u);
-      const PrimV pv = c2p(u, fix);
-      R Fp[5], Fm[5];
-      split_flux<R, AX>(u, pv, Fp, Fm);
+  // (1) lane = (line, point m < 4); point m starts a run when its cell
+  // differs from point m-1's (points 4..7 are in point 3's run)
+  const int l1 = tid >> 2, m1 = tid & 3;
+  const long long L1 = (long long)blockIdx.x * kBoundLines + l1;
+  const bool act1 = tid < kBoundLines * 4 && L1 < nlines && (m1 == 0 || bound_cell(n, m1) != bound_cell(n, m1 - 1));
+  // the face adjoint of lane (line, field, split) of step (2) and the G of
+  // the run's cell, loaded first so that their latency overlaps step (1)
+  const int l2 = tid / 10, r2 = tid % 10, c2 = r2 >> 1, sp2 = r2 & 1;
+  const long long L2 = (long long)blockIdx.x * kBoundLines + l2;
+  R phi = R(0);
+  if (L2 < nlines && !(c2 == 4 && a.skip_n)) {
+    long long stride;
+    const long long base = line_base(AX, L2, a.g, stride);
+    phi = -a.mu[c2 * nc + base + (long long)(n - 1) * stride] * a.inv_d;
+  }
+  R u[5], gpre[5];
+  double eo = 0.0;
+  bool fixed = false;
+  long long cell1 = 0;
+  if (act1) {
+    long long stride;
+    cell1 = line_base(AX, L1, a.g, stride) + (long long)bound_cell(n, m1) * stride;
 #pragma unroll
-      for (int c = 0; c < 5; ++c) {
-        sF[l][m][c] = Fp[c];
-        sF[l][m][5 + c] = Fm[c];
-      }
+    for (int c = 0; c < 5; ++c) gpre[c] = a.G[c * nc + cell1];
+    load5(a.W, nc, cell1, u);
+    const unsigned f0 = fix;
+    const PrimV pv = c2p(u, fix);
+    eo = pv.e;
+    fixed = fix != f0;
+    R Fp[5], Fm[5];
+    split_flux<R, AX>(u, pv, Fp, Fm);
+#pragma unroll
+    for (int c = 0; c < 5; ++c) {
+      sF[l1][m1][c] = Fp[c];
+      sF[l1][m1][5 + c] = Fm[c];
     }
   }
   __syncthreads();
   // (2) reconstruction adjoints, lane = (line, field, split)
   {
-    const int l = tid / 10, r = tid % 10, c = r >> 1, sp = r & 1;
-    const long long L = (long long)blockIdx.x * kBoundLines + l;
-    if (L < nlines) {
-      long long stride;
-      const long long base = line_base(AX, L, a.g, stride);
-      const R phi = (c == 4 && a.skip_n) ? R(0) : -a.mu[c * nc + base + (long long)(n - 1) * stride] * a.inv_d;
+    const int l = l2, c = c2, sp = sp2;
+    if (L2 < nlines) {
       R args[7], ab[7];
       if (sp == 0) {
 #pragma unroll
-        for (int m = 0; m < 7; ++m) args[m] = sF[l][m][c];
+        for (int m = 0; m < 7; ++m) args[m] = sF[l][bound_rep(n, m)][c];
         weno7_vjp<R, S>(args, phi, a.eps, ab);
 #pragma unroll
         for (int m = 0; m < 7; ++m) sA[l][m][c] = (double)ab[m];
         sA[l][7][c] = 0.0;
       } else {
 #pragma unroll
-        for (int m = 0; m < 7; ++m) args[m] = sF[l][7 - m][5 + c];
+        for (int m = 0; m < 7; ++m) args[m] = sF[l][bound_rep(n, 7 - m)][5 + c];
         weno7_vjp<R, S>(args, phi, a.eps, ab);
 #pragma unroll
         for (int m = 0; m < 7; ++m) sA[l][7 - m][5 + c] = (double)ab[m];
@@ -567,43 +598,24 @@ __global__ void __launch_bounds__(kBoundLines * 10) k_bound_adj(AdjArgs<R> a) {
     }
   }
   __syncthreads();
-  // (3) split-flux adjoint per point, lane = (line, point); result over sF
-  R u[5];
-  double ub[5];
-  const int l3 = tid >> 3, m3 = tid & 7;
-  const long long L3 = (long long)blockIdx.x * kBoundLines + l3;
-  const bool act3 = tid < kBoundLines * 8 && L3 < nlines;
-  if (act3) {
-    long long stride;
-    const long long base = line_base(AX, L3, a.g, stride);
-    load5(a.W, nc, base + (long long)map_idx(n - 4 + m3, n, 0) * stride, u);
-    const PrimJ J = c2p_jac((double)u[0], (double)u[1], (double)u[2], (double)u[3]);
-    double ap[5], am[5];
+  // (3) the run's adjoints in point order, the split-flux adjoint, G
+  if (act1) {
+    double ap[5], am[5], ub[5];
 #pragma unroll
-    for (int c = 0; c < 5; ++c) {
-      ap[c] = sA[l3][m3][c];
-      am[c] = sA[l3][m3][5 + c];
-    }
-    split_flux_vjp<R, AX>(u, J, ap, am, ub);
-  }
-  __syncthreads();  // every lane has read sF/sA
-  if (act3) {
+    for (int c = 0; c < 5; ++c) ap[c] = am[c] = 0.0;
+    const int k = bound_cell(n, m1);
+    for (int m = m1; m < 8 && bound_cell(n, m) == k; ++m) {
 #pragma unroll
-    for (int c = 0; c < 5; ++c) sF[l3][m3][c] = (R)ub[c];
-  }
-  __syncthreads();
-  // (4) add to G, lane = (line, field), points in order
-  if (tid < kBoundLines * 5) {
-    const int l = tid / 5, c = tid % 5;
-    const long long L = (long long)blockIdx.x * kBoundLines + l;
-    if (L < nlines) {
-      long long stride;
-      const long long base = line_base(AX, L, a.g, stride);
-      for (int m = 0; m < 8; ++m) {
-        R* gp = a.G + c * nc + base + (long long)map_idx(n - 4 + m, n, 0) * stride;
-        *gp = *gp + sF[l][m][c];
+      for (int c = 0; c < 5; ++c) {
+        ap[c] = ap[c] + sA[l1][m][c];
+        am[c] = am[c] + sA[l1][m][5 + c];
       }
     }
+    const double E = (double)u[0], Mx = (double)u[1], My = (double)u[2], Mz = (double)u[3];
+    const PrimJ J = fixed ? c2p_jac(E, Mx, My, Mz) : c2p_jac_known(E, Mx, My, Mz, eo);
+    split_flux_vjp<R, AX>(u, J, ap, am, ub);
+#pragma unroll
+    for (int c = 0; c < 5; ++c) a.G[c * nc + cell1] = gpre[c] + (R)ub[c];
   }
   add_fixups(a.fixups, fix);
 }
@@ -619,8 +631,9 @@ __global__ void __launch_bounds__(512) k_jet_adj(JetAdjArgs a) {
   const long long nc = a.g.nc;
   const double dV = a.g.dx[0] * a.g.dx[1] * a.g.dx[2];
   const double hc = a.hbarc;
-  __shared__ double red[12][512];
-  __shared__ double wax[3][7], dwax[3][7];
+  __shared__ double red[8][12];  // per-wave sums
+  __shared__ double tot[12];     // the workgroup's sums
+  __shared__ double wraw[3][7], wax[3][7], dwax[3][7];
   __shared__ int ctr_s[3];
   __shared__ int inside_s;
   const int t = threadIdx.x;
@@ -628,33 +641,40 @@ __global__ void __launch_bounds__(512) k_jet_adj(JetAdjArgs a) {
     const JetDev jt = a.s->jets[j];
     const bool chi = a.Ehist[j] > 0.0;
     const double ell = a.t - jt.t_start;
-    if (t == 0) {
-      int in = (chi && ell >= 0.0) ? 1 : 0;
-      for (int d = 0; d < 3; ++d) {
-        const double x = jt.x0[d] + jt.dir[d] * ell;
-        const int c = ngp_index(x, a.g.n[d], a.g.dx[d]);
-        ctr_s[d] = c;
-        if (c < 0) in = 0;
-        if (a.deposit == 1) {
-          const double sig2 = a.g.dx[d] * a.g.dx[d];
-          double sum = 0.0, dsum = 0.0;
-          for (int m = 0; m < 7; ++m) {
-            const double del = cell_centre(c - 3 + m, a.g.n[d], a.g.dx[d]) - x;
-            wax[d][m] = exp(-(del * del) / (2.0 * sig2));
-            sum = sum + wax[d][m];
-          }
-          for (int m = 0; m < 7; ++m) wax[d][m] = wax[d][m] / sum;
-          for (int m = 0; m < 7; ++m) {
-            const double del = cell_centre(c - 3 + m, a.g.n[d], a.g.dx[d]) - x;
-            dsum += wax[d][m] * del / sig2;
-          }
-          for (int m = 0; m < 7; ++m) {
-            const double del = cell_centre(c - 3 + m, a.g.n[d], a.g.dx[d]) - x;
-            dwax[d][m] = wax[d][m] * (del / sig2 - dsum);  // d w_m / d x
-          }
-        }
+    // footprint weights: lane t < 21 takes axis t / 7, offset t % 7 (the
+    // sums over the seven offsets in offset order, as one lane would)
+    const int wd = t / 7, wm = t % 7;
+    // the lane's axis by selects (an index by wd would put the structs in
+    // scratch memory)
+    auto pick = [wd](double v0, double v1, double v2) { return wd == 0 ? v0 : (wd == 1 ? v1 : v2); };
+    const int wn = wd == 0 ? a.g.n[0] : (wd == 1 ? a.g.n[1] : a.g.n[2]);
+    const double wdx = pick(a.g.dx[0], a.g.dx[1], a.g.dx[2]);
+    double wx = 0.0, wdel = 0.0, wsig2 = 1.0;
+    if (t < 21) {
+      wx = pick(jt.x0[0], jt.x0[1], jt.x0[2]) + pick(jt.dir[0], jt.dir[1], jt.dir[2]) * ell;
+      const int c = ngp_index(wx, wn, wdx);
+      if (wm == 0) ctr_s[wd] = c;
+      wsig2 = wdx * wdx;
+      wdel = cell_centre(c - 3 + wm, wn, wdx) - wx;
+      if (a.deposit == 1) wraw[wd][wm] = exp(-(wdel * wdel) / (2.0 * wsig2));
+    }
+    __syncthreads();
+    if (t == 0) inside_s = (chi && ell >= 0.0 && ctr_s[0] >= 0 && ctr_s[1] >= 0 && ctr_s[2] >= 0) ? 1 : 0;
+    if (a.deposit == 1) {
+      if (t < 21) {
+        double sum = 0.0;
+        for (int m = 0; m < 7; ++m) sum = sum + wraw[wd][m];
+        wax[wd][wm] = wraw[wd][wm] / sum;
       }
-      inside_s = in;
+      __syncthreads();
+      if (t < 21) {
+        double dsum = 0.0;
+        for (int m = 0; m < 7; ++m) {
+          const double del = cell_centre(ctr_s[wd] - 3 + m, wn, wdx) - wx;
+          dsum += wax[wd][m] * del / wsig2;
+        }
+        dwax[wd][wm] = wax[wd][wm] * (wdel / wsig2 - dsum);  // d w_m / d x
+      }
     }
     __syncthreads();
     if (inside_s) {
@@ -697,20 +717,26 @@ __global__ void __launch_bounds__(512) k_jet_adj(JetAdjArgs a) {
                    jt.dir[2] * (double)mu[3 * nc + cell]) / dV;
           }
         }
-        // reductions: 0 wsum, 1 sum wT, 2 sum sig w, 3-5 sum sig dw, 6-8 sum dw T, 9-11 sum dw
-        const double vals[12] = {w, w * T, sig * w, sig * dw[0], sig * dw[1], sig * dw[2],
-                                 dw[0] * T, dw[1] * T, dw[2] * T, dw[0], dw[1], dw[2]};
-        for (int r = 0; r < 12; ++r) red[r][t] = vals[r];
-        __syncthreads();
-        for (int h = 256; h > 0; h >>= 1) {
-          if (t < h)
-            for (int r = 0; r < 12; ++r) red[r][t] = red[r][t] + red[r][t + h];
-          __syncthreads();
+        // reductions: 0 wsum, 1 sum wT, 2 sum sig w, 3-5 sum sig dw, 6-8 sum dw T, 9-11 sum dw;
+        // butterfly within each wave, then lane r < 12 adds the eight waves in order
+#pragma unroll
+        for (int r = 0; r < 12; ++r) {
+          double v = r == 0 ? w : r == 1 ? w * T : r == 2 ? sig * w : r < 6 ? sig * dw[r - 3] : r < 9 ? dw[r - 6] * T : dw[r - 9];
+#pragma unroll
+          for (int off = 32; off > 0; off >>= 1) v = v + __shfl_xor(v, off, 64);
+          if ((t & 63) == 0) red[t >> 6][r] = v;
         }
-        const double wsum = red[0][0];
-        const double Tj = red[1][0] / wsum;
+        __syncthreads();
+        if (t < 12) {
+          double v = red[0][t];
+          for (int wv = 1; wv < 8; ++wv) v = v + red[wv][t];
+          tot[t] = v;
+        }
+        __syncthreads();
+        const double wsum = tot[0];
+        const double Tj = tot[1] / wsum;
         const double Pj = energy_loss(jt, Tj, ell, hc);
-        const double dJdP = red[2][0];
+        const double dJdP = tot[2];
         const double dPdT = 2.0 * jt.kappa_coll * jt.crcf * Tj / hc + 3.0 * jt.kappa_rad * jt.crcf * Tj * Tj * ell / (hc * hc);
         const double dJdT = dJdP * dPdT;
         if (cell >= 0) {
@@ -726,8 +752,8 @@ __global__ void __launch_bounds__(512) k_jet_adj(JetAdjArgs a) {
           gr[0] += a.bdt * dJdP * jt.crcf * Tj * Tj * Tj * ell / (hc * hc);
           gr[1] += a.bdt * dJdP * jt.crcf * Tj * Tj / hc;
           for (int d = 0; d < 3; ++d) {
-            const double dTj = (red[6 + d][0] - Tj * red[9 + d][0]) / wsum;
-            gr[2 + d] += a.bdt * (Pj * red[3 + d][0] + dJdT * dTj);
+            const double dTj = (tot[6 + d] - Tj * tot[9 + d]) / wsum;
+            gr[2 + d] += a.bdt * (Pj * tot[3 + d] + dJdT * dTj);
           }
         }
       }
@@ -888,28 +914,58 @@ void launch_bound_adj(int AX, const AdjArgs<R>& a, long long nl, hipStream_t st)
   if (AX == 2) hipLaunchKernelGGL((k_bound_adj<R, S, 2>), dim3(nbb), tb, 0, st, a);
 }
 
+// Lines per workgroup of a line adjoint along AX: 1 for x lines (contiguous);
+// for y and z lines the request (automatic: 2, the most that keeps five
+// 2-wave-or-larger workgroups' worth of LDS per CU at n = 128) or fewer, so
+// that n_x is a multiple, the workgroup has at most 1024 lanes and its LDS
+// stays within 64 KiB.
+template <class R>
+int line_adj_lines(int AX, const AdjArgs<R>& a) {
+  if (AX == 0) return 1;
+  const int n = a.g.n[AX];
+  int nl = a.lines > 0 ? a.lines : 2;
+  while (nl > 1 && (a.g.n[0] % nl != 0 || n * nl > 1024 ||
+                    (size_t)line_adj_pitch(n, nl) * nl * sizeof(R) > 65536))
+    nl /= 2;
+  return nl;
+}
+
+template <class R, int S, int AX, int NL>
+void launch_line_adj(const AdjArgs<R>& a, hipStream_t st) {
+  const int n = a.g.n[AX];
+  const long long nlines = AX == 0 ? (long long)a.g.n[1] * a.g.n[2]
+                                   : (AX == 1 ? (long long)a.g.n[0] * a.g.n[2] : (long long)a.g.n[0] * a.g.n[1]);
+  const long long ng = nlines / NL;
+  const int tb = ((n * NL + 63) / 64) * 64;
+  const size_t lds = (size_t)line_adj_pitch(n, NL) * NL * sizeof(R);
+  const unsigned nb = (unsigned)(((ng + 7) / 8) * 8);
+  if (tb <= 256)
+    hipLaunchKernelGGL((k_line_adj<R, S, AX, 256, NL>), dim3(nb), dim3(tb), lds, st, a);
+  else
+    hipLaunchKernelGGL((k_line_adj<R, S, AX, 1024, NL>), dim3(nb), dim3(tb), lds, st, a);
+}
+
 template <class R, int S>
 void launch_adj_axis_t(int AX, const AdjArgs<R>& a0, hipStream_t st) {
   AdjArgs<R> a = a0;
   a.inv_d = R(1.0 / a.g.dx[AX]);
-  const int n = a.g.n[AX];
   const long long nl = AX == 0 ? (long long)a.g.n[1] * a.g.n[2]
                                : (AX == 1 ? (long long)a.g.n[0] * a.g.n[2] : (long long)a.g.n[0] * a.g.n[1]);
-  const int tb = ((n + 63) / 64) * 64;
-  const size_t lds = (size_t)line_adj_lds_elems(n) * sizeof(R);
-  const unsigned nb = (unsigned)(((nl + 7) / 8) * 8);
   // The outflow face n-1/2 adds to G: before the line kernel when that one
   // finishes G (fused combine), after it when that one starts G (first).
   const bool bound = a.g.bc[AX] == 0;
   if (bound && a.stage != 0) launch_bound_adj<R, S>(AX, a, nl, st);
-  if (tb <= 256) {
-    if (AX == 0) hipLaunchKernelGGL((k_line_adj<R, S, 0, 256>), dim3(nb), dim3(tb), lds, st, a);
-    if (AX == 1) hipLaunchKernelGGL((k_line_adj<R, S, 1, 256>), dim3(nb), dim3(tb), lds, st, a);
-    if (AX == 2) hipLaunchKernelGGL((k_line_adj<R, S, 2, 256>), dim3(nb), dim3(tb), lds, st, a);
-  } else {
-    if (AX == 0) hipLaunchKernelGGL((k_line_adj<R, S, 0, 1024>), dim3(nb), dim3(tb), lds, st, a);
-    if (AX == 1) hipLaunchKernelGGL((k_line_adj<R, S, 1, 1024>), dim3(nb), dim3(tb), lds, st, a);
-    if (AX == 2) hipLaunchKernelGGL((k_line_adj<R, S, 2, 1024>), dim3(nb), dim3(tb), lds, st, a);
+  const int lines = line_adj_lines<R>(AX, a);
+  if (AX == 0) launch_line_adj<R, S, 0, 1>(a, st);
+  if (AX == 1) {
+    if (lines == 4) launch_line_adj<R, S, 1, 4>(a, st);
+    else if (lines == 2) launch_line_adj<R, S, 1, 2>(a, st);
+    else launch_line_adj<R, S, 1, 1>(a, st);
+  }
+  if (AX == 2) {
+    if (lines == 4) launch_line_adj<R, S, 2, 4>(a, st);
+    else if (lines == 2) launch_line_adj<R, S, 2, 2>(a, st);
+    else launch_line_adj<R, S, 2, 1>(a, st);
   }
   if (bound && a.stage == 0) launch_bound_adj<R, S>(AX, a, nl, st);
 }

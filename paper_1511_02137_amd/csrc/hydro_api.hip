@@ -53,6 +53,7 @@ struct hydro_ctx {
   int yz_tile = 1;   // 1: y/z faces from LDS tiles, 0: register-window marches
   int x_tile = 0;    // 1: x faces from 32 x 16 LDS tiles, 0: one row per workgroup
   int adj_skip_n = 0;  // 1: the adjoint sweep takes lambda_N as zero and skips N
+  int adj_lines = 0;   // lines per workgroup of the y/z line adjoints (0: automatic)
   int tile_order = 2;  // HYDRO_OPT_TILE_ORDER: z tiles step the transverse axis (measured 6 % faster)
   std::string err;
   // per-kernel timing (hydro_profile): event pairs recorded around launches
@@ -346,6 +347,7 @@ int adjoint_impl(hydro_ctx* ctx, const R* Uc, int64_t step0, const double* E0, i
   a.acc = acc;
   a.stage = 0;
   a.skip_n = ctx->adj_skip_n;
+  a.lines = ctx->adj_lines;
   const double cst[3] = {0.0, 1.0, 0.5};
   const double bst[3] = {1.0, 0.25, 2.0 / 3.0};
   for (int i = K - 1; i >= 0; --i) {
@@ -838,6 +840,11 @@ int hydro_set_option(hydro_ctx* ctx, int option, int value) {
       if (value < 0 || value > 3) return fail(ctx, HYDRO_EINVAL, "HYDRO_OPT_TILE_ORDER takes 0..3");
       ctx->tile_order = value;
       return HYDRO_OK;
+    case HYDRO_OPT_ADJ_LINES:
+      if (value != 0 && value != 1 && value != 2 && value != 4)
+        return fail(ctx, HYDRO_EINVAL, "HYDRO_OPT_ADJ_LINES takes 0, 1, 2 or 4");
+      ctx->adj_lines = value;
+      return HYDRO_OK;
     default:
       return fail(ctx, HYDRO_EINVAL, "unknown option");
   }
@@ -851,6 +858,7 @@ int hydro_get_option(hydro_ctx* ctx, int option, int* value) {
     case HYDRO_OPT_X_KERNEL: *value = ctx->x_tile; return HYDRO_OK;
     case HYDRO_OPT_ADJ_SKIP_N: *value = ctx->adj_skip_n; return HYDRO_OK;
     case HYDRO_OPT_TILE_ORDER: *value = ctx->tile_order; return HYDRO_OK;
+    case HYDRO_OPT_ADJ_LINES: *value = ctx->adj_lines; return HYDRO_OK;
     default: return fail(ctx, HYDRO_EINVAL, "unknown option");
   }
 }

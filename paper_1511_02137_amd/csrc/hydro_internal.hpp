@@ -183,12 +183,22 @@ struct AdjArgs {
   // skipped and its outputs (G, lW, acc) are zero.  N enters no other field's
   // flux and no source, so with a zero N adjoint on entry this is exact.
   int skip_n;
+  // lines per workgroup of the y and z line adjoints requested by the caller
+  // (0: automatic; 1, 2 or 4); the launcher takes fewer where they do not fit
+  int lines;
 };
 
 // LDS of the line adjoint kernel, in elements of the field type: split fluxes
 // [2][5][n+8] and the face partials of both splits [2][7][n+16] (face x at
 // x+8, zero pads so the gather needs no bounds tests).
 constexpr long long line_adj_lds_elems(int n) { return 10LL * (n + 8) + 14LL * (n + 16); }
+// Elements between the LDS areas of the nl lines of one line-adjoint
+// workgroup: padded so that neighbouring lines' copies of a slot are 32/nl
+// four-byte banks apart.
+constexpr long long line_adj_pitch(int n, int nl) {
+  return nl == 1 ? line_adj_lds_elems(n)
+                 : line_adj_lds_elems(n) + ((32 / nl - line_adj_lds_elems(n) % 32) % 32 + 32) % 32;
+}
 
 // Arguments of the jet-source adjoint kernel.
 struct JetAdjArgs {

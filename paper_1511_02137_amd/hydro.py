@@ -33,7 +33,7 @@ EXPORTED = [
     "hydro_batch_sums", "hydro_batch_get_state", "hydro_batch_diag", "hydro_batch_last_error",
     "hydro_batch_destroy", "hydro_sums_noalloc", "hydro_freezeout",
 ]
-OPT_YZ_KERNEL, OPT_MARCH_SEG, OPT_X_KERNEL, OPT_ADJ_SKIP_N, OPT_TILE_ORDER = 0, 1, 2, 3, 4
+OPT_YZ_KERNEL, OPT_MARCH_SEG, OPT_X_KERNEL, OPT_ADJ_SKIP_N, OPT_TILE_ORDER, OPT_ADJ_LINES = 0, 1, 2, 3, 4, 5
 BOPT_BLOCKS_X, BOPT_BLOCKS_Y, BOPT_BLOCKS_Z, BOPT_GRAPH, BOPT_X_ROWS = 0, 1, 2, 3, 4
 KERNELS = ["xface", "xbound", "ymarch", "jet", "zmarch", "sums", "adjoint"]
 

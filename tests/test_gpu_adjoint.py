@@ -400,6 +400,43 @@ def test_skip_n_option_is_exact_for_zero_n_adjoint():
             h.close()
 
 
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+@pytest.mark.parametrize("bc", ["outflow", "periodic"])
+def test_adjoint_lines_per_workgroup_bitwise(precision, bc):
+    """HYDRO_OPT_ADJ_LINES: the y and z line adjoints with 1, 2 or 4
+    neighbouring lines per workgroup return the same bits (lambda and the
+    parameter gradients), here with n_x = 20 (a multiple of 4) and ragged
+    y/z extents; an unsupported value is refused."""
+    from paper_1511_02137_amd import hydro as H
+    steps = 2
+    w = small(n=(20, 18, 13), steps=steps)
+    pb = oracle_problem(w)
+    dt = torch.float64 if precision == "f64" else torch.float32
+    U0 = torch.tensor(O.prim_to_cons(pb, w.prim0), dtype=dt, device="cuda")
+    Wt = np.stack([smooth_direction(pb.shape, 90 + f) for f in range(5)])
+    outs = []
+    for lines in (1, 2, 4, 0):
+        h = H.from_workload(w, precision=precision, bc=(bc,) * 3, adjoint_k=steps)
+        h.set_option(H.OPT_ADJ_LINES, lines)
+        assert h.get_option(H.OPT_ADJ_LINES) == lines
+        lam = torch.tensor(Wt, dtype=dt, device="cuda")
+        grad = torch.zeros((1, 5), dtype=torch.float64, device="cuda")
+        h.adjoint_step(U0, 0, [w.jets[0].E0], steps, lam, grad)
+        torch.cuda.synchronize()
+        outs.append((lam.cpu().numpy(), grad.cpu().numpy()))
+        h.close()
+    assert np.any(outs[0][0]) and np.any(outs[0][1])
+    for o in outs[1:]:
+        assert np.array_equal(o[0], outs[0][0])
+        assert np.array_equal(o[1], outs[0][1])
+    h = H.from_workload(w, precision=precision)
+    try:
+        with pytest.raises(H.HydroError):
+            h.set_option(H.OPT_ADJ_LINES, 3)
+    finally:
+        h.close()
+
+
 def test_torch_gradcheck_small():
     """torch.autograd.gradcheck (fast mode: random projections of the Jacobian
     against central differences of the GPU forward, eps 1e-6) of the
