@@ -322,10 +322,11 @@ typedef enum {
                                tiles) set = neighbouring workgroups share the tile index and step the
                                transverse axis, clear = they step along the axis; default 2 */
   HYDRO_OPT_ADJ_LINES = 5   /* lines per workgroup of the y and z line adjoints: 0 = automatic
-                               (default, 2), 1, 2 or 4; fewer where n_x is not a multiple or the
-                               workgroup would exceed 1024 lanes or 64 KiB of LDS.  Neighbouring x
-                               lines share the workgroup, so their strided loads share cache lines;
-                               every line is computed by the same arithmetic (same results) */
+                               (default: 2 in FP32, 1 in FP64), 1, 2 or 4; fewer where n_x is not a
+                               multiple or the workgroup would exceed 1024 lanes or 64 KiB of LDS.
+                               Neighbouring x lines share the workgroup, so their strided loads
+                               share cache lines; every line is computed by the same arithmetic
+                               (same results) */
 } hydro_option;
 
 /* Set / read an option; HYDRO_EINVAL for an unknown option or bad value. */

@@ -915,15 +915,17 @@ void launch_bound_adj(int AX, const AdjArgs<R>& a, long long nl, hipStream_t st)
 }
 
 // Lines per workgroup of a line adjoint along AX: 1 for x lines (contiguous);
-// for y and z lines the request (automatic: 2, the most that keeps five
-// 2-wave-or-larger workgroups' worth of LDS per CU at n = 128) or fewer, so
-// that n_x is a multiple, the workgroup has at most 1024 lanes and its LDS
-// stays within 64 KiB.
+// for y and z lines the request or fewer, so that n_x is a multiple, the
+// workgroup has at most 1024 lanes and its LDS stays within 64 KiB.
+// Automatic: 2 in FP32 (at n = 128 five such workgroups fit a CU's LDS, the
+// occupancy of one line per workgroup, and the strided loads fetch half the
+// cache lines: 128^3 backward 170 -> 150 ms; 4 lines: 156 ms), 1 in FP64
+// (twice the LDS per line: two lines cost a workgroup per CU, 3 % slower).
 template <class R>
 int line_adj_lines(int AX, const AdjArgs<R>& a) {
   if (AX == 0) return 1;
   const int n = a.g.n[AX];
-  int nl = a.lines > 0 ? a.lines : 2;
+  int nl = a.lines > 0 ? a.lines : (sizeof(R) == 4 ? 2 : 1);
   while (nl > 1 && (a.g.n[0] % nl != 0 || n * nl > 1024 ||
                     (size_t)line_adj_pitch(n, nl) * nl * sizeof(R) > 65536))
     nl /= 2;
