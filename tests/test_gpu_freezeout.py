@@ -63,12 +63,16 @@ def test_small_event_after_its_run(precision):
 
 
 @pytest.mark.parametrize("n_phi,pt,n_harm", [
-    (1, [], 0),                      # one output: 255 lane groups
-    (3, [0.7], 1),                   # 6 outputs, ragged groups
-    (48, [0.4, 2.2], 12),            # 144 outputs: one group, lanes 144..255 idle
-    (256, [], 32),                   # one output per lane
-    (100, [0.3, 0.9, 1.5], 20),      # 400 outputs: two per lane, second partly owned
-    (64, list(np.linspace(0.2, 4.0, 15)), 31),  # the maximum, 1024 outputs
+    # n_phi <= 256: lanes own azimuths, 256 // n_phi groups split the cells
+    (1, [], 0),                      # one azimuth: 256 groups
+    (3, [0.7], 1),                   # 85 groups, lane 255 idle
+    (48, [0.4, 2.2], 12),            # 5 groups, lanes 240..255 idle
+    (256, [], 32),                   # one group
+    (100, [0.3, 0.9, 1.5], 20),      # 2 groups, lanes 200..255 idle
+    (64, list(np.linspace(0.2, 4.0, 15)), 31),  # the most rows, 1024 outputs
+    # n_phi > 256: lanes own outputs (row, azimuth), up to four each
+    (300, [0.5, 1.5], 8),            # 900 outputs: four per lane, the last partly owned
+    (1024, [], 16),                  # the most azimuths
 ])
 def test_output_shapes_and_ragged_grids(n_phi, pt, n_harm):
     w = W.small_event(1, n=(21, 18, 13), steps=3)  # 4914 cells: not a multiple of 256
