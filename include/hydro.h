@@ -153,7 +153,8 @@ void hydro_default_config(hydro_config* cfg);
 
 /* Bytes of caller-provided device workspace that hydro_init needs for cfg:
  * two stage states and one flux-divergence field (15 words per cell) plus
- * reduction partials (conservation sums, eps2, freeze-out: 8 MiB).  adjoint_k > 0 adds room for the 3*adjoint_k stage
+ * reduction partials (conservation sums, eps2, freeze-out: 8 MiB).
+ * adjoint_k > 0 adds room for the 3*adjoint_k stage
  * states one hydro_adjoint_step of adjoint_k steps recomputes and for the
  * adjoint fields.  Returns 0 for an invalid cfg. */
 size_t hydro_workspace_bytes(const hydro_config* cfg, int adjoint_k);
@@ -187,7 +188,8 @@ int hydro_add_jet(hydro_ctx* ctx, const hydro_jet* jet, int* jet_id);
  * the flux divergence of the component-wise WENO7 reconstruction of the
  * Lax-Friedrichs split fluxes F+- = (f +- U)/2 (alpha = 1) plus the jet
  * source.  After each step the jet energies and the deposited-energy ledger
- * advance by dt (P1/6 + P2/6 + 2 P3/3) and the FP64 sums of U dV are taken. */
+ * advance by dt (P1/6 + P2/6 + 2 P3/3) and the FP64 sums of U dV are taken
+ * (hydro_step_sums). */
 int hydro_rk3_step(hydro_ctx* ctx, void* U, int nsteps, void* stream);
 
 /* Right-hand side of one stage, L(U) = D(U) + S(U) at time t, into L
@@ -210,6 +212,14 @@ int hydro_primitives(hydro_ctx* ctx, const void* U, void* prim, void* stream);
  * Returns HYDRO_ENONPHYS when a sum is not finite (a NaN or infinity in U,
  * out still written) and, in strict mode, after a fix-up. */
 int hydro_sums(hydro_ctx* ctx, const void* U, double out[6], void* stream);
+
+/* The same totals as taken by the last hydro_rk3_step on ctx (section
+ * "Simulation setup"; zero before the first step and after hydro_reset).
+ * Synchronous: out[0..4] = sums of E, Mx, My, Mz, N times dV of U after that
+ * step (the kernels and order of hydro_sums, so bit for bit its values for
+ * that U), out[5] = deposited-energy ledger.  HYDRO_ENONPHYS when a sum is
+ * not finite. */
+int hydro_step_sums(hydro_ctx* ctx, double out[6]);
 
 /* Freeze-out: particles from the evolved fluid and their flow harmonics,
  * the step the paper plans next (section "Results", closing paragraph: add

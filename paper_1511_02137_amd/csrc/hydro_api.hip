@@ -269,7 +269,7 @@ int step_impl(hydro_ctx* ctx, R* U, int nsteps, hipStream_t st) {
     hipError_t e;
     {
       ProfScope p(ctx, HYDRO_K_SUMS, st);
-      e = launch_sums<R>(U, ctx->g.nc, dV, ctx->part, ctx->dev, st);
+      e = launch_sums<R>(U, ctx->g.nc, dV, ctx->part, ctx->dev->step_sums, st);
     }
     if (e != hipSuccess) return hip_fail(ctx, e, "sums launch");
     ctx->step += 1;
@@ -613,8 +613,8 @@ int hydro_sums(hydro_ctx* ctx, const void* U, double out[6], void* stream) {
   hipStream_t st = static_cast<hipStream_t>(stream);
   const double dV = ctx->cfg.dx[0] * ctx->cfg.dx[1] * ctx->cfg.dx[2];
   hipError_t e = ctx->cfg.precision == HYDRO_F32
-                     ? launch_sums<float>(static_cast<const float*>(U), ctx->g.nc, dV, ctx->part, ctx->dev, st)
-                     : launch_sums<double>(static_cast<const double*>(U), ctx->g.nc, dV, ctx->part, ctx->dev, st);
+                     ? launch_sums<float>(static_cast<const float*>(U), ctx->g.nc, dV, ctx->part, ctx->dev->sums, st)
+                     : launch_sums<double>(static_cast<const double*>(U), ctx->g.nc, dV, ctx->part, ctx->dev->sums, st);
   if (e != hipSuccess) return hip_fail(ctx, e, "hydro_sums launch");
   e = hipStreamSynchronize(st);
   if (e != hipSuccess) return hip_fail(ctx, e, "hydro_sums sync");
@@ -639,11 +639,25 @@ int hydro_sums_noalloc(hydro_ctx* ctx, const void* U, double* out, void* stream)
   hipStream_t st = static_cast<hipStream_t>(stream);
   const double dV = ctx->cfg.dx[0] * ctx->cfg.dx[1] * ctx->cfg.dx[2];
   hipError_t e = ctx->cfg.precision == HYDRO_F32
-                     ? launch_sums<float>(static_cast<const float*>(U), ctx->g.nc, dV, part, ctx->dev, st)
-                     : launch_sums<double>(static_cast<const double*>(U), ctx->g.nc, dV, part, ctx->dev, st);
+                     ? launch_sums<float>(static_cast<const float*>(U), ctx->g.nc, dV, part, ctx->dev->sums, st)
+                     : launch_sums<double>(static_cast<const double*>(U), ctx->g.nc, dV, part, ctx->dev->sums, st);
   if (e == hipSuccess) e = launch_copy_f64(ctx->dev->sums, out, 5, st);
   if (e == hipSuccess) e = launch_copy_f64(&ctx->dev->ledger, out + 5, 1, st);
   if (e != hipSuccess) return hip_fail(ctx, e, "hydro_sums_noalloc launch");
+  return HYDRO_OK;
+}
+
+int hydro_step_sums(hydro_ctx* ctx, double out[6]) {
+  if (!ctx || !out) return fail(ctx, HYDRO_EINVAL, "bad arguments to hydro_step_sums");
+  hipError_t e = hipDeviceSynchronize();
+  if (e != hipSuccess) return hip_fail(ctx, e, "hydro_step_sums sync");
+  DevScalars h;
+  e = hipMemcpy(&h, ctx->dev, sizeof(DevScalars), hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return hip_fail(ctx, e, "hydro_step_sums copy");
+  for (int c = 0; c < 5; ++c) out[c] = h.step_sums[c];
+  out[5] = h.ledger;
+  for (int c = 0; c < 6; ++c)
+    if (!std::isfinite(out[c])) return fail(ctx, HYDRO_ENONPHYS, "non-finite sums (NaN or infinity in the state)");
   return HYDRO_OK;
 }
 
@@ -744,6 +758,8 @@ int hydro_reset(hydro_ctx* ctx, const double* prim0, void* U, void* stream) {
   if (e == hipSuccess && ctx->njet > 0)
     e = hipMemcpy(ctx->dev->E_jet, E0, (size_t)ctx->njet * sizeof(double), hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(&ctx->dev->ledger, &zero, sizeof(double), hipMemcpyHostToDevice);
+  const double zeros[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  if (e == hipSuccess) e = hipMemcpy(ctx->dev->step_sums, zeros, sizeof(zeros), hipMemcpyHostToDevice);
   if (e != hipSuccess) return hip_fail(ctx, e, "hydro_reset");
   ctx->step = 0;
   return HYDRO_OK;

@@ -112,7 +112,7 @@ hipError_t launch_face_kernel(int kernel, const StageArgs<R>& a, int scheme, int
 template <class R>
 hipError_t launch_jet(const JetArgs& a, hipStream_t st);
 template <class R>
-hipError_t launch_sums(const R* U, long long nc, double dV, double* part, DevScalars* s, hipStream_t st);
+hipError_t launch_sums(const R* U, long long nc, double dV, double* part, double* sums, hipStream_t st);
 template <class R>
 hipError_t launch_prim_to_cons(const double* prim, R* U, long long nc, hipStream_t st);
 template <class R>

@@ -44,7 +44,8 @@ struct DevScalars {
   double E_jet[kMaxJets];     // remaining energy
   double P[3][kMaxJets];      // deposited rate of each stage of the current step
   double ledger;              // deposited energy so far
-  double sums[5];             // last conservation sums (x dV)
+  double sums[5];             // conservation sums (x dV) of the last hydro_sums call
+  double step_sums[5];        // conservation sums (x dV) taken by the last RK3 step
   unsigned long long fixups;  // conserved->primitive fix-ups
   unsigned long long fixups_save;  // fixups on entry to an adjoint sweep (restored on exit)
 };

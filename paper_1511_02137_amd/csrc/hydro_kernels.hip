@@ -874,7 +874,7 @@ __global__ void __launch_bounds__(256) k_sums_partial(const R* __restrict__ U, l
   sums_partial_body<R>(U, nc, part, blockIdx.x, gridDim.x);
 }
 
-__device__ __forceinline__ void sums_final_body(const double* part, int nblocks, double dV, DevScalars* s) {
+__device__ __forceinline__ void sums_final_body(const double* part, int nblocks, double dV, double* sums) {
   __shared__ double red[5][4];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   for (int c = 0; c < 5; ++c) {
@@ -886,12 +886,12 @@ __device__ __forceinline__ void sums_final_body(const double* part, int nblocks,
   __syncthreads();
   if (threadIdx.x < 5) {
     const int c = threadIdx.x;
-    s->sums[c] = ((red[c][0] + red[c][1]) + (red[c][2] + red[c][3])) * dV;
+    sums[c] = ((red[c][0] + red[c][1]) + (red[c][2] + red[c][3])) * dV;
   }
 }
 
-__global__ void __launch_bounds__(256) k_sums_final(const double* part, int nblocks, double dV, DevScalars* s) {
-  sums_final_body(part, nblocks, dV, s);
+__global__ void __launch_bounds__(256) k_sums_final(const double* part, int nblocks, double dV, double* sums) {
+  sums_final_body(part, nblocks, dV, sums);
 }
 
 // ---------------------------------------------------------------------------
@@ -1100,7 +1100,7 @@ __global__ void __launch_bounds__(256) k_bsums_partial(BatchArgs<R> b) {
 template <class R>
 __global__ void __launch_bounds__(256) k_bsums_final(BatchArgs<R> b) {
   const BatchEvent& ev = b.ev[blockIdx.x];
-  sums_final_body(ev.part, kSumBlocks, ev.dV, ev.dev);
+  sums_final_body(ev.part, kSumBlocks, ev.dV, ev.dev->sums);
 }
 
 __global__ void k_bstep(long long* step) {
@@ -1217,9 +1217,9 @@ hipError_t launch_jet(const JetArgs& a, hipStream_t st) {
 }
 
 template <class R>
-hipError_t launch_sums(const R* U, long long nc, double dV, double* part, DevScalars* s, hipStream_t st) {
+hipError_t launch_sums(const R* U, long long nc, double dV, double* part, double* sums, hipStream_t st) {
   hipLaunchKernelGGL((k_sums_partial<R>), dim3(kSumBlocks), dim3(256), 0, st, U, nc, part);
-  hipLaunchKernelGGL(k_sums_final, dim3(1), dim3(256), 0, st, part, kSumBlocks, dV, s);
+  hipLaunchKernelGGL(k_sums_final, dim3(1), dim3(256), 0, st, part, kSumBlocks, dV, sums);
   return hipGetLastError();
 }
 
@@ -1339,7 +1339,7 @@ hipError_t launch_batch_sums(const BatchArgs<R>& b, long long* step, hipStream_t
   template hipError_t launch_batch_sums<R>(const BatchArgs<R>&, long long*, hipStream_t);              \
   template hipError_t launch_face_kernel<R>(int, const StageArgs<R>&, int, int, hipStream_t);          \
   template hipError_t launch_jet<R>(const JetArgs&, hipStream_t);                                     \
-  template hipError_t launch_sums<R>(const R*, long long, double, double*, DevScalars*, hipStream_t); \
+  template hipError_t launch_sums<R>(const R*, long long, double, double*, double*, hipStream_t);     \
   template hipError_t launch_prim_to_cons<R>(const double*, R*, long long, hipStream_t);              \
   template hipError_t launch_primitives<R>(const R*, R*, long long, double, double, unsigned long long*, hipStream_t);
 

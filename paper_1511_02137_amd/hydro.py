@@ -31,7 +31,7 @@ EXPORTED = [
     "hydro_init_vjp", "hydro_batch_workspace_bytes", "hydro_batch_create", "hydro_batch_add_jet", "hydro_batch_run",
     "hydro_batch_rhs", "hydro_batch_set_option", "hydro_batch_get_option", "hydro_batch_autotune",
     "hydro_batch_sums", "hydro_batch_get_state", "hydro_batch_diag", "hydro_batch_last_error",
-    "hydro_batch_destroy", "hydro_sums_noalloc", "hydro_freezeout",
+    "hydro_batch_destroy", "hydro_sums_noalloc", "hydro_freezeout", "hydro_step_sums",
 ]
 OPT_YZ_KERNEL, OPT_MARCH_SEG, OPT_X_KERNEL, OPT_ADJ_SKIP_N, OPT_TILE_ORDER, OPT_ADJ_LINES = 0, 1, 2, 3, 4, 5
 BOPT_BLOCKS_X, BOPT_BLOCKS_Y, BOPT_BLOCKS_Z, BOPT_GRAPH, BOPT_X_ROWS = 0, 1, 2, 3, 4
@@ -112,6 +112,7 @@ def load_library(path: str = LIB_PATH):
     lib.hydro_rhs.argtypes = [vp, vp, ctypes.c_double, vp, vp]
     lib.hydro_sums.argtypes = [vp, vp, dp, vp]
     lib.hydro_sums_noalloc.argtypes = [vp, vp, vp, vp]
+    lib.hydro_step_sums.argtypes = [vp, dp]
     lib.hydro_freezeout.argtypes = [vp, vp, ctypes.POINTER(FreezeoutParams), vp, vp, vp]
     lib.hydro_get_state.argtypes = [vp, dp, ctypes.POINTER(ctypes.c_int64), dp, ctypes.c_int]
     lib.hydro_set_state.argtypes = [vp, ctypes.c_int64, dp, ctypes.c_int, ctypes.c_double]
@@ -328,6 +329,12 @@ class Hydro:
         U = self.U if U is None else U
         out = (ctypes.c_double * 6)()
         self._check(self.lib.hydro_sums(self.ctx, U.data_ptr(), out, _stream_handle(stream)))
+        return np.array(list(out))
+
+    def step_sums(self) -> np.ndarray:
+        """hydro_step_sums: the sums taken by the last step and the ledger."""
+        out = (ctypes.c_double * 6)()
+        self._check(self.lib.hydro_step_sums(self.ctx, out))
         return np.array(list(out))
 
     def sums_noalloc(self, out, U=None, stream=None):

@@ -217,6 +217,30 @@ def test_conservation_and_energy_budget_periodic():
     assert abs(s1[4] - s0[4]) <= 1e-13 * s0[4]
 
 
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+@pytest.mark.parametrize("yz", [0, 1])
+def test_step_sums(precision, yz):
+    """hydro_step_sums: the sums the last step took are hydro_sums' of the
+    step's output bit for bit (LDS tiles and register marches), within
+    1e-12 of the oracle's in FP64; zero before the first step and after a
+    reset; the ledger is hydro_sums'."""
+    w = W.small_event(2, n=(37, 29, 45), steps=4)
+    w.jets[0].x0 = (-0.5, 0.0123, -0.0071)
+    h = H().from_workload(w, precision=precision)
+    h.set_option(H().OPT_YZ_KERNEL, yz)
+    assert np.all(h.step_sums()[:5] == 0.0)
+    h.step(4)
+    ss, su = h.step_sums(), h.sums()
+    assert np.array_equal(ss, su)
+    if precision == "f64":
+        pb, st = run_oracle(w, 4)
+        ref = np.asarray(O.sums(pb, st.U))
+        assert np.abs(ss[:5] - ref).max() <= 1e-12 * np.abs(ref).max()
+    h.reset(torch.from_numpy(w.prim0))
+    assert np.all(h.step_sums()[:5] == 0.0)
+    h.close()
+
+
 def test_restart_bitwise_gpu():
     w = W.small_event(1, n=(16, 16, 16))
     a = H().from_workload(w)
