@@ -363,6 +363,56 @@ def test_adjoint_step_dot_product_with_oracle_jvp(weno, bc):
         assert abs(np.sum(lam0[f] * V[f]) - np.sum(Wt * JVf)) <= 1e-10 * scale, f
 
 
+@pytest.mark.parametrize("n", [(20, 300, 6), (20, 6, 300)])
+def test_long_lines_dot_product_with_oracle_jvp(n):
+    """Lines longer than 256 cells take the line adjoint's 1024-lane form
+    (FP64: one line per workgroup, 320 lanes): the same dot-product check as
+    above, two steps, WENO-Z, outflow."""
+    from paper_1511_02137_amd import hydro as H
+    steps = 2
+    w = small(n=n, steps=steps)
+    pb = O.Problem(n=w.n, dx=w.dx, t0=w.t0, dt=w.dt, bc=("outflow",) * 3, deposit=w.deposit)
+    U0 = O.prim_to_cons(pb, w.prim0)
+    amp = np.abs(U0).max(axis=(1, 2, 3))[:, None, None, None]
+    V = np.stack([smooth_direction(pb.shape, 140 + f) for f in range(5)]) * amp
+    Wt = np.stack([smooth_direction(pb.shape, 160 + f) for f in range(5)]) / amp
+    _, JV = O.jvp(pb, U0, V, steps, oracle_jets(w))
+    print("long lines", w.n, flush=True)
+    h = H.from_workload(w, precision="f64", adjoint_k=steps)
+    lam = torch.tensor(Wt, dtype=torch.float64, device="cuda")
+    grad = torch.zeros((1, 5), dtype=torch.float64, device="cuda")
+    h.adjoint_step(torch.tensor(U0, dtype=torch.float64, device="cuda"), 0, [w.jets[0].E0], steps, lam, grad)
+    torch.cuda.synchronize()
+    lam0 = lam.cpu().numpy()
+    h.close()
+    lhs, rhs, scale = np.sum(lam0 * V), np.sum(Wt * JV), np.sum(np.abs(Wt * JV))
+    print("lhs %.15e rhs %.15e rel %.2e" % (lhs, rhs, abs(lhs - rhs) / scale), flush=True)
+    assert abs(lhs - rhs) <= 1e-10 * scale, (lhs, rhs, scale)
+
+
+def test_long_lines_fp32_lines_per_workgroup_bitwise():
+    """FP32 z lines of 300 cells: one and two lines per workgroup (320 and
+    640 lanes, the 1024-lane form) give the same bits."""
+    from paper_1511_02137_amd import hydro as H
+    steps = 2
+    w = small(n=(20, 6, 300), steps=steps)
+    pb = oracle_problem(w)
+    U0 = torch.tensor(O.prim_to_cons(pb, w.prim0), dtype=torch.float32, device="cuda")
+    Wt = np.stack([smooth_direction(pb.shape, 180 + f) for f in range(5)])
+    outs = []
+    for lines in (1, 2):
+        h = H.from_workload(w, precision="f32", adjoint_k=steps)
+        h.set_option(H.OPT_ADJ_LINES, lines)
+        lam = torch.tensor(Wt, dtype=torch.float32, device="cuda")
+        grad = torch.zeros((1, 5), dtype=torch.float64, device="cuda")
+        h.adjoint_step(U0, 0, [w.jets[0].E0], steps, lam, grad)
+        torch.cuda.synchronize()
+        outs.append((lam.cpu().numpy(), grad.cpu().numpy()))
+        h.close()
+    assert np.any(outs[0][0])
+    assert np.array_equal(outs[0][0], outs[1][0]) and np.array_equal(outs[0][1], outs[1][1])
+
+
 def test_skip_n_option_is_exact_for_zero_n_adjoint():
     """HYDRO_OPT_ADJ_SKIP_N: with lambda_N = 0 on entry the skipping sweep
     returns the general sweep's result (values equal, N component zero); with
