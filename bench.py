@@ -185,6 +185,15 @@ def precision_check(n: int, steps: int):
     return out
 
 
+# Algorithmic flops of one reconstruction's adjoint (WENO7-Z; add and
+# multiply 1, fma 2): the forward recomputed (155, as in FLOPS_PER_CELL) and
+# the reverse sweep (122: the partials of the normalised sum in the weights
+# and candidates 6, through the Z weights to tau and the indicators 34, the
+# indicators to the nested differences 34, the candidates to the first
+# differences 24, the transposed differences to the seven points 24).
+ADJ_FLOPS_RECON = 155 + 122
+
+
 def adjoint_ratio(precision: str, n: int, steps: int, ckpt: int, repeats: int = 3):
     """Differentiable run (workloads.gradient_event): forward = reset, the
     steps with a checkpoint every `ckpt` steps, eps2; backward = loss seed,
@@ -243,10 +252,22 @@ def adjoint_ratio(precision: str, n: int, steps: int, ckpt: int, repeats: int = 
              "blob_direction_rel_vs_f64": abs(d32 - d64) / abs(d64),
              "blob_direction": "exp(-|x - (-1, 0, 0)|^2 / (2 * 0.5^2)), x in fm",
              "f64_blob_derivative": d64}
+    # the line adjoints' arithmetic rate: reverse-WENO flops of a launch
+    # (ADJ_FLOPS_RECON per reconstruction, 4 fields (N's adjoint is zero for
+    # eps2 and skipped) x 2 splits per cell) over the mean time of the line and
+    # boundary-face adjoint launches of one axis (HIP events)
+    t_adj, n_adj = prof.get("adjoint", (0.0, 0))
+    flops_launch = float(n) ** 3 * 4 * 2 * ADJ_FLOPS_RECON
+    adj_tf = flops_launch / (t_adj / n_adj * 1e-3) / 1e12 if n_adj else 0.0
+    peak = PEAK_TFLOPS[precision]
     out = {"workload": "%s: %d^3, %d steps, checkpoint every %d, %s fields, FP64 parameter gradients"
                        % (w.name, n, steps, ckpt, precision),
            "forward_ms": 1e3 * min(tf), "backward_ms": 1e3 * min(tb), "ratio": min(tb) / min(tf),
            "backward_kernels_ms": {k: t for k, (t, c) in prof.items() if c},
+           "line_adjoint_roofline": {"bound": "alu", "kernel": "line adjoints (one launch per axis and stage)",
+                                     "flops_per_cell": 4 * 2 * ADJ_FLOPS_RECON,
+                                     "ms_per_launch": t_adj / n_adj if n_adj else None,
+                                     "achieved": adj_tf, "peak": peak, "unit": "TFLOP/s", "frac": adj_tf / peak},
            "eps2": float(eps.item()),
            "grad": {"kappa_rad": g[0], "kappa_coll": g[1], "x0": g[2], "y0": g[3]},
            "e_init_grad": einit}
