@@ -139,10 +139,11 @@ __global__ void __launch_bounds__(kFoThreads) k_fo_partial(FreezeArgs<R> a) {
 // against extended-precision exp on 2e7 points of [-745, 0]); 0 below -745.2,
 // where e^x rounds to zero.
 __device__ __forceinline__ double exp_neg(double x, const double* tab) {
-  const double t = rint(x * 46.16624130844683);  // x 32/ln2
+  const double xc = fmax(x, -746.0);  // keeps t within int (below -745.2 the result is 0 anyway)
+  const double t = rint(xc * 46.16624130844683);  // x 32/ln2
   const int n = (int)t;
   const int j = n & 31, k = n >> 5;
-  const double r = fma(-t, -0x1.718432a1b0e26p-40, fma(-t, 0x1.62e42ff000000p-6, x));
+  const double r = fma(-t, -0x1.718432a1b0e26p-40, fma(-t, 0x1.62e42ff000000p-6, xc));
   double p = fma(r, 1.0 / 720.0, 1.0 / 120.0);
   p = fma(r, p, 1.0 / 24.0);
   p = fma(r, p, 1.0 / 6.0);

@@ -75,6 +75,15 @@ __device__ __forceinline__ R rk_out(int stage, R p, R dz, R dt, const R* Un, lon
   if (stage == 2) return R(0.75) * Un[i] + R(0.25) * v;
   return R(1.0 / 3.0) * Un[i] + R(2.0 / 3.0) * v;
 }
+// the same with U^n already read (un; used in stages 2 and 3 only)
+template <class R>
+__device__ __forceinline__ R rk_out_v(int stage, R p, R dz, R dt, R un) {
+  if (stage == 0) return p + dz;
+  const R v = fma(dt, dz, p);
+  if (stage == 1) return v;
+  if (stage == 2) return R(0.75) * un + R(0.25) * v;
+  return R(1.0 / 3.0) * un + R(2.0 / 3.0) * v;
+}
 
 template <class R, int S, bool PAIRS>
 __device__ __forceinline__ void xrows_body(const StageArgs<R>& a, long long row0, int rpi, R* s) {
@@ -595,6 +604,14 @@ __device__ __forceinline__ void tile_body(const StageArgs<R>& a, int bx, int by,
   }
 
   if (own_ok) {
+    // LAST, stages 2 and 3: the five U^n values are read before any output
+    // is stored (out may be U^n itself, so the compiler would otherwise keep
+    // each read behind the previous field's store: five round trips)
+    R unv[5];
+    if (LAST && a.stage >= 2) {
+#pragma unroll
+      for (int c = 0; c < 5; ++c) unv[c] = a.Un[c * nc + cell];
+    }
 #pragma unroll
     for (int c = 0; c < 5; ++c) {
       const int i0 = (c * kFP + ta) * kTileXP + tx, i1 = i0 + kTileXP;
@@ -604,7 +621,7 @@ __device__ __forceinline__ void tile_body(const StageArgs<R>& a, int bx, int by,
       if (!LAST) {
         a.D[c * nc + cell] = dpre[c] + div;
       } else {
-        a.out[c * nc + cell] = rk_out(a.stage, dpre[c], div, a.dt, a.Un, c * nc + cell);
+        a.out[c * nc + cell] = rk_out_v(a.stage, dpre[c], div, a.dt, unv[c]);
       }
     }
   }
