@@ -235,9 +235,10 @@ int hydro_step_sums(hydro_ctx* ctx, double out[6]);
  * summed over the cells with T >= T_min.  harm (may be NULL) [1 + n_pt]
  * [n_harm + 1][2]: harm[r][0] = (dN/dy of row r by the trapezoid rule
  * (2 pi/n_phi) sum_k, 0), harm[r][n] = (sum_k cos(n phi_k) s_k, sum_k
- * sin(n phi_k) s_k) / sum_k s_k of row r: v_n is the modulus of that pair,
- * its angle / n the n-th event-plane angle (x = the reaction plane of the
- * initial ellipsoid).  Both outputs are device FP64, written asynchronously;
+ * sin(n phi_k) s_k) / sum_k s_k of row r (0 when the row is empty: no
+ * cell at or above T_min): v_n is the modulus of that pair, its angle / n
+ * the n-th event-plane angle (x = the reaction plane of the initial
+ * ellipsoid).  Both outputs are device FP64, written asynchronously;
  * primitives are recovered in FP64 (fix-ups counted as in hydro_primitives).
  * Fixed reduction order (run-to-run identical).  Limits: 0 <= n_pt <= 15,
  * (1 + n_pt) n_phi <= 1024, 0 <= n_harm <= 32 with 2 n_harm < n_phi,

@@ -872,8 +872,9 @@ void flow_harmonics(const double* s, int n_phi, int n_harm, double* out) {
       cs += std::cos(ang) * s[k];
       sn += std::sin(ang) * s[k];
     }
-    out[2 * n] = cs / tot;
-    out[2 * n + 1] = sn / tot;
+    // a row with no particles (every cell below T_min) has no flow: 0, not 0/0
+    out[2 * n] = tot != 0.0 ? cs / tot : 0.0;
+    out[2 * n + 1] = tot != 0.0 ? sn / tot : 0.0;
   }
 }
 

@@ -284,8 +284,8 @@ __global__ void __launch_bounds__(64) k_fo_harm(const double* spectra, int n_phi
     cs = fma(cv, s[k], cs);
     sn = fma(sv, s[k], sn);
   }
-  h[0] = cs / tot;
-  h[1] = sn / tot;
+  h[0] = tot != 0.0 ? cs / tot : 0.0;  // no particles (every cell below T_min): no flow
+  h[1] = tot != 0.0 ? sn / tot : 0.0;
 }
 
 }  // namespace

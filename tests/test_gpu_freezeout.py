@@ -108,6 +108,17 @@ def test_repeatable_and_reading_only():
     h.close()
 
 
+def test_no_particles_above_every_cell():
+    """T_min above every cell's temperature: zero spectra, dN/dy and v_n
+    (0, not 0/0), as in the oracle."""
+    w = W.small_event(1, n=(12, 12, 12), steps=1)
+    h = H().from_workload(w)
+    spec, harm = h.freezeout(n_phi=16, pt=[1.0, 2.0], T_min=100.0, n_harm=4)
+    spec, harm = spec.cpu().numpy(), harm.cpu().numpy()
+    assert np.all(spec == 0.0) and np.all(harm == 0.0)
+    h.close()
+
+
 def test_argument_checks():
     w = W.small_event(1, n=(12, 12, 12), steps=1)
     h = H().from_workload(w)

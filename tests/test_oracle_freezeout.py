@@ -198,3 +198,6 @@ def test_tmin_drops_exactly_the_cold_cells():
     assert np.allclose(spec, sh, rtol=1e-13, atol=0)
     full, _, _ = O.freezeout(pb, O.prim_to_cons(pb, prim), n_phi=12, pt=[1.0])
     assert np.all(full > spec)
+    # T_min above every cell: no particles, dN/dy and every v_n zero (not 0/0)
+    none, harm, _ = O.freezeout(pb, O.prim_to_cons(pb, prim), n_phi=12, pt=[1.0], T_min=100.0, n_harm=4)
+    assert np.all(none == 0.0) and np.all(harm == 0.0)
