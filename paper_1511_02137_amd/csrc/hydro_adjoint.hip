@@ -681,6 +681,8 @@ __global__ void __launch_bounds__(512) k_jet_adj(JetAdjArgs a) {
       if (a.deposit == 0) {
         if (t == 0) {
           const long long cell = ((long long)ctr_s[2] * a.g.n[1] + ctr_s[1]) * a.g.n[0] + ctr_s[0];
+          R gv[4];  // the cell's G, read with its state
+          for (int k = 0; k < 4; ++k) gv[k] = G[k * nc + cell];
           const PrimJ J = c2p_jac((double)W[cell], (double)W[nc + cell], (double)W[2 * nc + cell],
                                   (double)W[3 * nc + cell]);
           const double T = temperature(J.e, a.eos_dof, hc);
@@ -691,8 +693,8 @@ __global__ void __launch_bounds__(512) k_jet_adj(JetAdjArgs a) {
           const double vb[3] = {0.0, 0.0, 0.0};
           double Eb, Mb[3];
           c2p_vjp(J, eb, vb, Eb, Mb);
-          G[cell] = G[cell] + (R)Eb;
-          for (int k = 0; k < 3; ++k) G[(1 + k) * nc + cell] = G[(1 + k) * nc + cell] + (R)Mb[k];
+          G[cell] = gv[0] + (R)Eb;
+          for (int k = 0; k < 3; ++k) G[(1 + k) * nc + cell] = gv[1 + k] + (R)Mb[k];
           double* gr = a.grad + 5 * j;
           gr[0] += a.bdt * sig * jt.crcf * T * T * T * ell / (hc * hc);
           gr[1] += a.bdt * sig * jt.crcf * T * T / hc;
@@ -702,6 +704,7 @@ __global__ void __launch_bounds__(512) k_jet_adj(JetAdjArgs a) {
         double w = 0.0, T = 0.0, sig = 0.0, dw[3] = {0.0, 0.0, 0.0};
         long long cell = -1;
         PrimJ J;
+        R gv[4];  // the cell's G, read with its state
         if (t < 343) {
           const int mi = t % 7, mj = (t / 7) % 7, mk = t / 49;
           const int i = ctr_s[0] - 3 + mi, jj = ctr_s[1] - 3 + mj, k = ctr_s[2] - 3 + mk;
@@ -711,6 +714,7 @@ __global__ void __launch_bounds__(512) k_jet_adj(JetAdjArgs a) {
             dw[0] = dwax[0][mi] * wax[1][mj] * wax[2][mk];
             dw[1] = wax[0][mi] * dwax[1][mj] * wax[2][mk];
             dw[2] = wax[0][mi] * wax[1][mj] * dwax[2][mk];
+            for (int q = 0; q < 4; ++q) gv[q] = G[q * nc + cell];
             J = c2p_jac((double)W[cell], (double)W[nc + cell], (double)W[2 * nc + cell], (double)W[3 * nc + cell]);
             T = temperature(J.e, a.eos_dof, hc);
             sig = ((double)mu[cell] + jt.dir[0] * (double)mu[nc + cell] + jt.dir[1] * (double)mu[2 * nc + cell] +
@@ -744,8 +748,8 @@ __global__ void __launch_bounds__(512) k_jet_adj(JetAdjArgs a) {
           const double vb[3] = {0.0, 0.0, 0.0};
           double Eb, Mb[3];
           c2p_vjp(J, eb, vb, Eb, Mb);
-          G[cell] = G[cell] + (R)Eb;
-          for (int k = 0; k < 3; ++k) G[(1 + k) * nc + cell] = G[(1 + k) * nc + cell] + (R)Mb[k];
+          G[cell] = gv[0] + (R)Eb;
+          for (int k = 0; k < 3; ++k) G[(1 + k) * nc + cell] = gv[1 + k] + (R)Mb[k];
         }
         if (t == 0) {
           double* gr = a.grad + 5 * j;

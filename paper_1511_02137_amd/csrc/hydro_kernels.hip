@@ -790,20 +790,22 @@ __device__ __forceinline__ void jet_body(const JetArgs& a) {
       if (a.deposit == 0) {
         if (threadIdx.x == 0) {
           const long long cell = ((long long)ctr_s[2] * a.g.n[1] + ctr_s[1]) * a.g.n[0] + ctr_s[0];
-          R u[5];
+          R u[5], dv[4];  // the cell's state and its D, read together
           load5(W, nc, cell, u);
+          for (int d = 0; d < 4; ++d) dv[d] = D[d * nc + cell];
           const PrimV pv = c2p(u, fix);
           const double T = temperature(pv.e, a.eos_dof, a.hbarc);
           P = energy_loss(jt, T, ell, a.hbarc);
           const double s0 = P / dV;
-          D[cell] = D[cell] + (R)s0;
-          for (int d = 0; d < 3; ++d) D[(1 + d) * nc + cell] = D[(1 + d) * nc + cell] + (R)(jt.dir[d] * s0);
+          D[cell] = dv[0] + (R)s0;
+          for (int d = 0; d < 3; ++d) D[(1 + d) * nc + cell] = dv[1 + d] + (R)(jt.dir[d] * s0);
         }
       } else {
         // 7^3 footprint, thread t < 343 owns cell (mi, mj, mk)
         const int t = threadIdx.x;
         double w = 0.0, wT = 0.0;
         long long cell = -1;
+        R dv[4];  // the cell's D, read with its state
         if (t < 343) {
           const int mi = t % 7, mj = (t / 7) % 7, mk = t / 49;
           const int i = ctr_s[0] - 3 + mi, jj = ctr_s[1] - 3 + mj, k = ctr_s[2] - 3 + mk;
@@ -812,6 +814,7 @@ __device__ __forceinline__ void jet_body(const JetArgs& a) {
             w = wax[0][mi] * wax[1][mj] * wax[2][mk];
             R u[5];
             load5(W, nc, cell, u);
+            for (int d = 0; d < 4; ++d) dv[d] = D[d * nc + cell];
             const PrimV pv = c2p(u, fix);
             wT = w * temperature(pv.e, a.eos_dof, a.hbarc);
           }
@@ -832,8 +835,8 @@ __device__ __forceinline__ void jet_body(const JetArgs& a) {
         P = Pj * wsum;
         if (cell >= 0) {
           const double s0 = Pj * w / dV;
-          D[cell] = D[cell] + (R)s0;
-          for (int d = 0; d < 3; ++d) D[(1 + d) * nc + cell] = D[(1 + d) * nc + cell] + (R)(jt.dir[d] * s0);
+          D[cell] = dv[0] + (R)s0;
+          for (int d = 0; d < 3; ++d) D[(1 + d) * nc + cell] = dv[1 + d] + (R)(jt.dir[d] * s0);
         }
       }
     }
