@@ -214,7 +214,8 @@ int hydro_primitives(hydro_ctx* ctx, const void* U, void* prim, void* stream);
 int hydro_sums(hydro_ctx* ctx, const void* U, double out[6], void* stream);
 
 /* The same totals as taken by the last hydro_rk3_step on ctx (section
- * "Simulation setup"; zero before the first step and after hydro_reset).
+ * "Simulation setup"; zero before the first step and after hydro_reset or
+ * hydro_set_state).
  * Synchronous: out[0..4] = sums of E, Mx, My, Mz, N times dV of U after that
  * step (the kernels and order of hydro_sums, so bit for bit its values for
  * that U), out[5] = deposited-energy ledger.  HYDRO_ENONPHYS when a sum is
@@ -273,7 +274,9 @@ int hydro_freezeout(hydro_ctx* ctx, const void* U, const hydro_freezeout_params*
  * checked here (no synchronisation); hydro_diag reports fix-ups. */
 int hydro_sums_noalloc(hydro_ctx* ctx, const void* U, double* out, void* stream);
 
-/* Synchronous: time, step index and the jets' remaining energies. */
+/* Synchronous: time, step index and the jets' remaining energies.
+ * hydro_set_state restores them with the ledger (a restart; the step sums
+ * read by hydro_step_sums become zero until the next step). */
 int hydro_get_state(hydro_ctx* ctx, double* t, int64_t* step, double* E_jet, int n_jet);
 int hydro_set_state(hydro_ctx* ctx, int64_t step, const double* E_jet, int n_jet, double ledger);
 

@@ -729,6 +729,9 @@ int hydro_set_state(hydro_ctx* ctx, int64_t step, const double* E_jet, int n_jet
   if (e == hipSuccess && n_jet > 0)
     e = hipMemcpy(ctx->dev->E_jet, E_jet, (size_t)n_jet * sizeof(double), hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(&ctx->dev->ledger, &ledger, sizeof(double), hipMemcpyHostToDevice);
+  // the step sums belonged to the state before the restart
+  const double zeros[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  if (e == hipSuccess) e = hipMemcpy(ctx->dev->step_sums, zeros, sizeof(zeros), hipMemcpyHostToDevice);
   if (e != hipSuccess) return hip_fail(ctx, e, "hydro_set_state");
   ctx->step = step;
   return HYDRO_OK;

@@ -223,7 +223,7 @@ def test_step_sums(precision, yz):
     """hydro_step_sums: the sums the last step took are hydro_sums' of the
     step's output bit for bit (LDS tiles and register marches), within
     1e-12 of the oracle's in FP64; zero before the first step and after a
-    reset; the ledger is hydro_sums'."""
+    reset or a restart (hydro_set_state); the ledger is hydro_sums'."""
     w = W.small_event(2, n=(37, 29, 45), steps=4)
     w.jets[0].x0 = (-0.5, 0.0123, -0.0071)
     h = H().from_workload(w, precision=precision)
@@ -236,6 +236,12 @@ def test_step_sums(precision, yz):
         pb, st = run_oracle(w, 4)
         ref = np.asarray(O.sums(pb, st.U))
         assert np.abs(ss[:5] - ref).max() <= 1e-12 * np.abs(ref).max()
+    _, step, Ej = h.get_state()
+    h.set_state(step, Ej, ss[5])
+    z = h.step_sums()
+    assert np.all(z[:5] == 0.0) and z[5] == ss[5]
+    h.step(1)
+    assert np.array_equal(h.step_sums(), h.sums())
     h.reset(torch.from_numpy(w.prim0))
     assert np.all(h.step_sums()[:5] == 0.0)
     h.close()
