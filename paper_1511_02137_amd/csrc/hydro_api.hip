@@ -551,13 +551,7 @@ int hydro_init(const hydro_config* cfg, const double* prim0, void* U, void* work
 int hydro_add_jet(hydro_ctx* ctx, const hydro_jet* jet, int* jet_id) {
   if (!ctx || !jet) return HYDRO_EINVAL;
   if (ctx->njet >= kMaxJets) return fail(ctx, HYDRO_EINVAL, "too many jets");
-  double n2 = jet->dir[0] * jet->dir[0] + jet->dir[1] * jet->dir[1] + jet->dir[2] * jet->dir[2];
-  if (!(std::fabs(n2 - 1.0) < 1e-9)) return fail(ctx, HYDRO_EINVAL, "jet direction must be a unit vector");
-  for (int d = 0; d < 3; ++d)
-    if (!std::isfinite(jet->x0[d])) return fail(ctx, HYDRO_EINVAL, "jet origin must be finite");
-  if (!(jet->E0 >= 0.0) || !std::isfinite(jet->t_start) || !std::isfinite(jet->kappa_rad) ||
-      !std::isfinite(jet->kappa_coll) || !std::isfinite(jet->cr_over_cf))
-    return fail(ctx, HYDRO_EINVAL, "bad jet parameters");
+  if (const char* why = jet_error(jet)) return fail(ctx, HYDRO_EINVAL, why);
   const int id = ctx->njet;
   JetDev jd;
   for (int d = 0; d < 3; ++d) {
@@ -770,8 +764,7 @@ int hydro_reset(hydro_ctx* ctx, const double* prim0, void* U, void* stream) {
 
 int hydro_set_jet(hydro_ctx* ctx, int id, const hydro_jet* jet) {
   if (!ctx || !jet || id < 0 || id >= ctx->njet) return fail(ctx, HYDRO_EINVAL, "bad arguments to hydro_set_jet");
-  double n2 = jet->dir[0] * jet->dir[0] + jet->dir[1] * jet->dir[1] + jet->dir[2] * jet->dir[2];
-  if (!(std::fabs(n2 - 1.0) < 1e-9)) return fail(ctx, HYDRO_EINVAL, "jet direction must be a unit vector");
+  if (const char* why = jet_error(jet)) return fail(ctx, HYDRO_EINVAL, why);
   JetDev jd;
   for (int d = 0; d < 3; ++d) {
     jd.x0[d] = jet->x0[d];

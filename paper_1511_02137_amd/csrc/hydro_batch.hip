@@ -441,13 +441,7 @@ int hydro_batch_add_jet(hydro_batch* b, int event, const hydro_jet* jet, int* je
   if (!b || !jet || event < 0 || event >= b->n) return bfail(b, HYDRO_EINVAL, "bad arguments to hydro_batch_add_jet");
   BatchEvent& v = b->ev[event];
   if (v.njet >= kMaxJets) return bfail(b, HYDRO_EINVAL, "too many jets");
-  const double n2 = jet->dir[0] * jet->dir[0] + jet->dir[1] * jet->dir[1] + jet->dir[2] * jet->dir[2];
-  if (!(std::fabs(n2 - 1.0) < 1e-9)) return bfail(b, HYDRO_EINVAL, "jet direction must be a unit vector");
-  for (int d = 0; d < 3; ++d)
-    if (!std::isfinite(jet->x0[d])) return bfail(b, HYDRO_EINVAL, "jet origin must be finite");
-  if (!(jet->E0 >= 0.0) || !std::isfinite(jet->t_start) || !std::isfinite(jet->kappa_rad) ||
-      !std::isfinite(jet->kappa_coll) || !std::isfinite(jet->cr_over_cf))
-    return bfail(b, HYDRO_EINVAL, "bad jet parameters");
+  if (const char* why = jet_error(jet)) return bfail(b, HYDRO_EINVAL, why);
   const int id = v.njet;
   JetDev jd;
   for (int d = 0; d < 3; ++d) {

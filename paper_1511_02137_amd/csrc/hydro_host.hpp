@@ -76,6 +76,19 @@ inline bool config_ok(const hydro_config* c, std::string* why) {
   return true;
 }
 
+// Checks of a jet's parameters (hydro_add_jet, hydro_set_jet,
+// hydro_batch_add_jet): nullptr when they are usable, else the reason.
+inline const char* jet_error(const hydro_jet* jet) {
+  const double n2 = jet->dir[0] * jet->dir[0] + jet->dir[1] * jet->dir[1] + jet->dir[2] * jet->dir[2];
+  if (!(std::fabs(n2 - 1.0) < 1e-9)) return "jet direction must be a unit vector";
+  for (int d = 0; d < 3; ++d)
+    if (!std::isfinite(jet->x0[d])) return "jet origin must be finite";
+  if (!(jet->E0 >= 0.0) || !std::isfinite(jet->t_start) || !std::isfinite(jet->kappa_rad) ||
+      !std::isfinite(jet->kappa_coll) || !std::isfinite(jet->cr_over_cf))
+    return "bad jet parameters";
+  return nullptr;
+}
+
 // Template scheme argument of the face kernels: the WENO scheme, plus kPP
 // with the positivity-preserving limiter, plus kMusta with MUSTA-FORCE fluxes.
 inline int face_scheme(const hydro_config& c) {

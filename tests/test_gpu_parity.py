@@ -552,3 +552,37 @@ def test_allocation_failure_returns_enomem_without_side_effects(monkeypatch):
     h = H().Hydro(cfg, prim)
     assert h.sums()[0] > 0
     h.close()
+
+
+def test_jet_parameter_checks():
+    """hydro_add_jet, hydro_set_jet and hydro_batch_add_jet refuse the same
+    unusable jets (a direction that is not a unit vector, a non-finite origin
+    or parameter, a negative energy) and leave the jets as they were."""
+    import torch
+    w = W.small_event(1, n=(12, 12, 12))
+    j = w.jets[0]
+    base = dict(x0=tuple(j.x0), dir=tuple(j.dir), E0=j.E0, t_start=j.t_start, kappa_rad=j.kappa_rad,
+                kappa_coll=j.kappa_coll, cr_over_cf=j.cr_over_cf)
+    nan, inf = float("nan"), float("inf")
+    bad = [dict(dir=(1.0, 0.1, 0.0)), dict(x0=(nan, 0.0, 0.0)), dict(x0=(0.0, inf, 0.0)), dict(E0=-1.0),
+           dict(E0=nan), dict(t_start=nan), dict(kappa_rad=inf), dict(kappa_coll=nan), dict(cr_over_cf=nan)]
+    h = H().from_workload(w)
+    b = H().batch_from_workloads([w], precision="f64")
+    for o in bad:
+        p = dict(base, **o)
+        print("bad jet", o, flush=True)
+        with pytest.raises(H().HydroError):
+            h.set_jet(0, **p)
+        with pytest.raises(H().HydroError):
+            h.add_jet(**p)
+        with pytest.raises(H().HydroError):
+            b.add_jet(0, **p)
+    assert h.get_state()[2][0] == j.E0
+    ref = H().from_workload(w)
+    h.step(2)
+    ref.step(2)
+    torch.cuda.synchronize()
+    assert torch.equal(h.U, ref.U)
+    h.close()
+    ref.close()
+    b.close()
