@@ -24,7 +24,11 @@
  *     caller.  The library owns only the opaque context: configuration, jet
  *     table and a few small device scalars (jet energies, ledger, sums).
  *   - Calls are asynchronous on `stream` (a hipStream_t; NULL = the default
- *     stream) unless stated otherwise.
+ *     stream) unless stated otherwise.  The calls on one context share its
+ *     workspace (the divergence buffer, reduction partials) and its device
+ *     scalars, so they are ordered by the caller: one stream, or a
+ *     synchronisation between streams.  Calls on one context that overlap
+ *     race; different contexts are independent.
  *   - Every function returns a hydro_status.  Argument errors return
  *     HYDRO_EINVAL before any side effect; HIP errors return HYDRO_EDEVICE
  *     and hydro_last_error() gives the HIP error text.  Nothing aborts or
