@@ -28,7 +28,8 @@
  *     workspace (the divergence buffer, reduction partials) and its device
  *     scalars, so they are ordered by the caller: one stream, or a
  *     synchronisation between streams.  Calls on one context that overlap
- *     race; different contexts are independent.
+ *     race; different contexts are independent (but for the static array
+ *     of hydro_sums_noalloc, below).
  *   - Every function returns a hydro_status.  Argument errors return
  *     HYDRO_EINVAL before any side effect; HIP errors return HYDRO_EDEVICE
  *     and hydro_last_error() gives the HIP error text.  Nothing aborts or
