@@ -320,6 +320,25 @@ int hydro_loss_eps2(hydro_ctx* ctx, const void* U, double* eps2_out, void* seed,
 int hydro_adjoint_step(hydro_ctx* ctx, const void* U_ckpt, int64_t step0, const double* E_jet0, int nsteps,
                        void* lambda, double* grad_jets, void* stream);
 
+/* The same reverse sweep without the recompute, for runs whose stage states
+ * fit in HBM.  hydro_rk3_step_record advances U by nsteps steps exactly as
+ * hydro_rk3_step does (Eq. (1)-(3), SSP-RK3; the same values bit for bit,
+ * step sums, jet energies and ledger included) and keeps every step's three
+ * stage states and its jet energies in the workspace's adjoint region (sized
+ * with hydro_workspace_bytes(cfg, adjoint_k >= nsteps); 3 nsteps states of U's
+ * size), replacing an earlier record.  hydro_adjoint_recorded then runs
+ * hydro_adjoint_step's sweep over the recorded steps: lambda (device, layout
+ * and type of U) in: dJ/dU after them, out: dJ/dU before them; grad_jets
+ * (device FP64 [n_jet][5]) is incremented; the result is bit for bit that of
+ * hydro_adjoint_step from the record's first state.  The record stays valid
+ * for further sweeps (other seeds) until hydro_adjoint_step, hydro_reset,
+ * hydro_set_state, hydro_add_jet or hydro_set_jet, after which
+ * hydro_adjoint_recorded returns HYDRO_ESTATE.  The same schemes and grid
+ * limits as hydro_adjoint_step (HYDRO_EINVAL otherwise); the context's U,
+ * step, jet energies and ledger are left unchanged by the sweep. */
+int hydro_rk3_step_record(hydro_ctx* ctx, void* U, int nsteps, void* stream);
+int hydro_adjoint_recorded(hydro_ctx* ctx, void* lambda, double* grad_jets, void* stream);
+
 /* Adjoint of the primitive->conserved map of hydro_init at prim0 (device
  * FP64 [5][nz][ny][nx]): grad_prim (device FP64, same layout) =
  * (dU/dprim)^T lambda, i.e. d/de, d/dvx, d/dvy, d/dvz, d/dn. */

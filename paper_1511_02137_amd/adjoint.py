@@ -30,17 +30,31 @@ class Checkpoint:
     E_jet: np.ndarray
 
 
+@dataclass
+class Recorded:
+    """Stands for the stage states a forward left in the workspace."""
+    generation: int
+
+
 class Eps2Problem:
     """A workload (workloads.Workload) set up for differentiation: one
     context whose workspace holds the stage states of `ckpt_every` steps, the
     fixed primitives (v, n) on the device, and jet 0's direction, energy and
-    start time (its kappas and origin are inputs of forward)."""
+    start time (its kappas and origin are inputs of forward).
 
-    def __init__(self, workload, precision: str = "f64", ckpt_every: int = 10, device: str = "cuda"):
+    record=True keeps the stage states of every step in HBM during the
+    forward (hydro_rk3_step_record; 3 steps states of U's size) so that the
+    backward runs the reverse sweep alone (hydro_adjoint_recorded, bit for bit
+    the checkpointed result); a backward then belongs to the latest forward."""
+
+    def __init__(self, workload, precision: str = "f64", ckpt_every: int = 10, device: str = "cuda",
+                 record: bool = False):
         import torch
         self.w = workload
         self.steps = int(workload.steps)
-        self.k = int(ckpt_every)
+        self.record = bool(record)
+        self.k = self.steps if self.record else int(ckpt_every)
+        self._generation = 0
         self.h = H.from_workload(workload, precision=precision, adjoint_k=self.k, device=device)
         # eps2 depends on e and v only, so the adjoint of N is zero throughout
         self.h.set_option(H.OPT_ADJ_SKIP_N, 1)
@@ -57,6 +71,10 @@ class Eps2Problem:
         prim[0] = e_init.detach().to(prim)
         self.set_params(kappa_rad, kappa_coll, x0, y0)
         self.h.reset(prim)
+        if self.record:
+            self.h.step_record(self.steps)
+            self._generation += 1
+            return self.h.loss_eps2(), [Recorded(self._generation)], self.h.U.clone(), prim
         cks: List[Checkpoint] = []
         s = 0
         while s < self.steps:
@@ -76,14 +94,21 @@ class Eps2Problem:
         differentiated re-applies them first (needed whenever another forward
         ran in between)."""
         import torch
-        if params is not None:
+        if self.record:
+            if len(cks) != 1 or not isinstance(cks[0], Recorded) or cks[0].generation != self._generation:
+                raise RuntimeError("another forward replaced the recorded stage states of this one "
+                                   "(record=False keeps checkpoints and allows interleaved forwards)")
+        elif params is not None:
             self.set_params(*params)
         lam = torch.empty_like(U_final)
         self.h.loss_eps2(U_final, seed=lam, scale=scale)
         grad = torch.zeros((max(1, self.h.njet), 5), dtype=torch.float64, device=U_final.device)
-        ends = [c.step for c in cks[1:]] + [self.steps]
-        for ck, end in reversed(list(zip(cks, ends))):
-            self.h.adjoint_step(ck.U, ck.step, ck.E_jet, end - ck.step, lam, grad)
+        if self.record:
+            self.h.adjoint_recorded(lam, grad)
+        else:
+            ends = [c.step for c in cks[1:]] + [self.steps]
+            for ck, end in reversed(list(zip(cks, ends))):
+                self.h.adjoint_step(ck.U, ck.step, ck.E_jet, end - ck.step, lam, grad)
         gprim = self.h.init_vjp(prim, lam)
         return gprim[0], grad
 

@@ -47,6 +47,10 @@ struct hydro_ctx {
   void* G = nullptr;
   double* Ehist = nullptr;  // [adj_k][kMaxJets]
   double* Esave = nullptr;  // [kMaxJets + 1]
+  // steps whose stage states and jet energies hydro_rk3_step_record left in
+  // the adjoint region (rec_n = 0: none, or overwritten since)
+  int64_t rec_step0 = 0;
+  int rec_n = 0;
   size_t field_bytes = 0;
   int64_t step = 0;
   int seg = 32;      // march segment length
@@ -296,33 +300,56 @@ bool adjoint_fits(const hydro_config* c, std::string* why) {
   return true;
 }
 
+#define HYDRO_TRY(x)                        \
+  do {                                      \
+    e = (x);                                \
+    if (e != hipSuccess) return hip_fail(ctx, e, #x); \
+  } while (0)
+
+// Stage state k (0: U^n, 1, 2: the inputs of stages 2 and 3) of step i of the
+// adjoint region.
+template <class R>
+R* state_ptr(hydro_ctx* ctx, int i, int k) {
+  return reinterpret_cast<R*>(ctx->states) + (size_t)(3 * i + k) * (ctx->field_bytes / sizeof(R));
+}
+
+// Keeps the context's jet energies, ledger and fix-up count: the recomputed
+// stages and the reverse kernels recover primitives again, which must not
+// count as new fix-ups of the run (8-byte moves, bit for bit).
+int adjoint_save(hydro_ctx* ctx, hipStream_t st) {
+  hipError_t e = hipSuccess;
+  HYDRO_TRY(launch_copy_f64(ctx->dev->E_jet, ctx->Esave, kMaxJets, st));
+  HYDRO_TRY(launch_copy_f64(&ctx->dev->ledger, ctx->Esave + kMaxJets, 1, st));
+  HYDRO_TRY(launch_copy_f64(reinterpret_cast<const double*>(&ctx->dev->fixups),
+                            reinterpret_cast<double*>(&ctx->dev->fixups_save), 1, st));
+  return HYDRO_OK;
+}
+
+int adjoint_restore(hydro_ctx* ctx, hipStream_t st) {
+  hipError_t e = hipSuccess;
+  HYDRO_TRY(launch_copy_f64(ctx->Esave, ctx->dev->E_jet, kMaxJets, st));
+  HYDRO_TRY(launch_copy_f64(ctx->Esave + kMaxJets, &ctx->dev->ledger, 1, st));
+  HYDRO_TRY(launch_copy_f64(reinterpret_cast<const double*>(&ctx->dev->fixups_save),
+                            reinterpret_cast<double*>(&ctx->dev->fixups), 1, st));
+  return HYDRO_OK;
+}
+
+// Reverse sweep over the K steps from step0 whose stage states and jet
+// energies are in the adjoint region.
+template <class R>
+int sweep_impl(hydro_ctx* ctx, int64_t step0, int K, R* lam, double* grad, hipStream_t st);
+
 template <class R>
 int adjoint_impl(hydro_ctx* ctx, const R* Uc, int64_t step0, const double* E0, int K, R* lam, double* grad,
                  hipStream_t st) {
   const hydro_config& c = ctx->cfg;
   const double dt = c.dt;
   const long long n5 = 5 * ctx->g.nc;
-  const size_t fe = ctx->field_bytes / sizeof(R);  // elements per state block
-  R* S = reinterpret_cast<R*>(ctx->states);
-  auto st_ptr = [&](int i, int k) { return S + (size_t)(3 * i + k) * fe; };
-  R* lamA = static_cast<R*>(ctx->lamA);
-  R* lamB = static_cast<R*>(ctx->lamB);
-  R* acc = static_cast<R*>(ctx->lacc);
-  R* G = static_cast<R*>(ctx->G);
+  auto st_ptr = [&](int i, int k) { return state_ptr<R>(ctx, i, k); };
   hipError_t e = hipSuccess;
-#define HYDRO_TRY(x)                        \
-  do {                                      \
-    e = (x);                                \
-    if (e != hipSuccess) return hip_fail(ctx, e, #x); \
-  } while (0)
-  // keep the context's jet energies and ledger
-  HYDRO_TRY(launch_copy_f64(ctx->dev->E_jet, ctx->Esave, kMaxJets, st));
-  HYDRO_TRY(launch_copy_f64(&ctx->dev->ledger, ctx->Esave + kMaxJets, 1, st));
-  // and its fix-up count: the recomputed stages and the reverse kernels
-  // recover primitives again, which must not count as new fix-ups of the run
-  // (an 8-byte move, bit for bit)
-  HYDRO_TRY(launch_copy_f64(reinterpret_cast<const double*>(&ctx->dev->fixups),
-                            reinterpret_cast<double*>(&ctx->dev->fixups_save), 1, st));
+  ctx->rec_n = 0;  // the recompute overwrites any recorded steps
+  int rc = adjoint_save(ctx, st);
+  if (rc != HYDRO_OK) return rc;
   // the checkpoint's jet energies (host memory): ordered after the saves above
   HYDRO_TRY(hipStreamSynchronize(st));
   if (ctx->njet > 0) HYDRO_TRY(hipMemcpy(ctx->dev->E_jet, E0, (size_t)ctx->njet * sizeof(double), hipMemcpyHostToDevice));
@@ -337,7 +364,56 @@ int adjoint_impl(hydro_ctx* ctx, const R* Uc, int64_t step0, const double* E0, i
     // sweep does not read (the jet energies are restored below)
     if (i + 1 < K) HYDRO_TRY(stage_impl<R>(ctx, st_ptr(i, 2), st_ptr(i, 0), st_ptr(i + 1, 0), 3, tn + 0.5 * dt, st));
   }
-  // reverse sweep
+  rc = sweep_impl<R>(ctx, step0, K, lam, grad, st);
+  if (rc != HYDRO_OK) return rc;
+  return adjoint_restore(ctx, st);
+}
+
+// Forward steps as step_impl, with the stage states of every step and the jet
+// energies at its start kept in the adjoint region (stage 3 writes the next
+// step's U^n there, the last one U), so that a reverse sweep needs no
+// recompute.  Bit for bit the values of step_impl.
+template <class R>
+int record_impl(hydro_ctx* ctx, R* U, int nsteps, hipStream_t st) {
+  const hydro_config& c = ctx->cfg;
+  const double dt = c.dt;
+  const long long n5 = 5 * ctx->g.nc;
+  const double cstage[3] = {0.0, 1.0, 0.5};
+  const double dV = c.dx[0] * c.dx[1] * c.dx[2];
+  auto st_ptr = [&](int i, int k) { return state_ptr<R>(ctx, i, k); };
+  hipError_t e = hipSuccess;
+  ctx->rec_n = 0;
+  const int64_t step0 = ctx->step;
+  HYDRO_TRY(launch_copy<R>(U, st_ptr(0, 0), n5, st));
+  for (int i = 0; i < nsteps; ++i) {
+    const double tn = c.t0 + (double)ctx->step * dt;
+    HYDRO_TRY(launch_copy_f64(ctx->dev->E_jet, ctx->Ehist + (size_t)i * kMaxJets, kMaxJets, st));
+    R* out3 = (i + 1 < nsteps) ? st_ptr(i + 1, 0) : U;
+    for (int k = 1; k <= 3; ++k) {
+      R* out = (k < 3) ? st_ptr(i, k) : out3;
+      HYDRO_TRY(stage_impl<R>(ctx, st_ptr(i, k - 1), st_ptr(i, 0), out, k, tn + cstage[k - 1] * dt, st));
+    }
+    {
+      ProfScope p(ctx, HYDRO_K_SUMS, st);
+      HYDRO_TRY(launch_sums<R>(out3, ctx->g.nc, dV, ctx->part, ctx->dev->step_sums, st));
+    }
+    ctx->step += 1;
+  }
+  ctx->rec_step0 = step0;
+  ctx->rec_n = nsteps;
+  return HYDRO_OK;
+}
+
+template <class R>
+int sweep_impl(hydro_ctx* ctx, int64_t step0, int K, R* lam, double* grad, hipStream_t st) {
+  const hydro_config& c = ctx->cfg;
+  const double dt = c.dt;
+  auto st_ptr = [&](int i, int k) { return state_ptr<R>(ctx, i, k); };
+  R* lamA = static_cast<R*>(ctx->lamA);
+  R* lamB = static_cast<R*>(ctx->lamB);
+  R* acc = static_cast<R*>(ctx->lacc);
+  R* G = static_cast<R*>(ctx->G);
+  hipError_t e = hipSuccess;
   AdjArgs<R> a;
   a.g = ctx->g;
   a.eps = (R)c.weno_eps;
@@ -387,13 +463,18 @@ int adjoint_impl(hydro_ctx* ctx, const R* Uc, int64_t step0, const double* E0, i
       }
     }
   }
-  HYDRO_TRY(launch_copy_f64(ctx->Esave, ctx->dev->E_jet, kMaxJets, st));
-  HYDRO_TRY(launch_copy_f64(ctx->Esave + kMaxJets, &ctx->dev->ledger, 1, st));
-  HYDRO_TRY(launch_copy_f64(reinterpret_cast<const double*>(&ctx->dev->fixups_save),
-                            reinterpret_cast<double*>(&ctx->dev->fixups), 1, st));
-#undef HYDRO_TRY
   return HYDRO_OK;
 }
+
+template <class R>
+int recorded_impl(hydro_ctx* ctx, R* lam, double* grad, hipStream_t st) {
+  int rc = adjoint_save(ctx, st);
+  if (rc != HYDRO_OK) return rc;
+  rc = sweep_impl<R>(ctx, ctx->rec_step0, ctx->rec_n, lam, grad, st);
+  if (rc != HYDRO_OK) return rc;
+  return adjoint_restore(ctx, st);
+}
+#undef HYDRO_TRY
 
 }  // namespace
 
@@ -567,6 +648,7 @@ int hydro_add_jet(hydro_ctx* ctx, const hydro_jet* jet, int* jet_id) {
   if (e != hipSuccess) return hip_fail(ctx, e, "hydro_add_jet");
   ctx->jets[id] = *jet;
   ctx->njet = id + 1;
+  ctx->rec_n = 0;
   if (jet_id) *jet_id = id;
   return HYDRO_OK;
 }
@@ -728,6 +810,7 @@ int hydro_set_state(hydro_ctx* ctx, int64_t step, const double* E_jet, int n_jet
   if (e == hipSuccess) e = hipMemcpy(ctx->dev->step_sums, zeros, sizeof(zeros), hipMemcpyHostToDevice);
   if (e != hipSuccess) return hip_fail(ctx, e, "hydro_set_state");
   ctx->step = step;
+  ctx->rec_n = 0;
   return HYDRO_OK;
 }
 
@@ -759,6 +842,7 @@ int hydro_reset(hydro_ctx* ctx, const double* prim0, void* U, void* stream) {
   if (e == hipSuccess) e = hipMemcpy(ctx->dev->step_sums, zeros, sizeof(zeros), hipMemcpyHostToDevice);
   if (e != hipSuccess) return hip_fail(ctx, e, "hydro_reset");
   ctx->step = 0;
+  ctx->rec_n = 0;
   return HYDRO_OK;
 }
 
@@ -779,6 +863,7 @@ int hydro_set_jet(hydro_ctx* ctx, int id, const hydro_jet* jet) {
   if (e == hipSuccess) e = hipMemcpy(&ctx->dev->E_jet[id], &jet->E0, sizeof(double), hipMemcpyHostToDevice);
   if (e != hipSuccess) return hip_fail(ctx, e, "hydro_set_jet");
   ctx->jets[id] = *jet;
+  ctx->rec_n = 0;
   return HYDRO_OK;
 }
 
@@ -817,6 +902,28 @@ int hydro_adjoint_step(hydro_ctx* ctx, const void* U_ckpt, int64_t step0, const 
                                grad_jets, st);
   return adjoint_impl<double>(ctx, static_cast<const double*>(U_ckpt), step0, E_jet0, nsteps,
                               static_cast<double*>(lambda), grad_jets, st);
+}
+
+int hydro_rk3_step_record(hydro_ctx* ctx, void* U, int nsteps, void* stream) {
+  if (!ctx || !U || nsteps < 1) return fail(ctx, HYDRO_EINVAL, "bad arguments to hydro_rk3_step_record");
+  if (nsteps > ctx->adj_k) return fail(ctx, HYDRO_EINVAL, "workspace holds fewer adjoint steps than nsteps");
+  std::string why;
+  if (!adjoint_fits(&ctx->cfg, &why)) return fail(ctx, HYDRO_EINVAL, why);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  if (ctx->cfg.precision == HYDRO_F32) return record_impl<float>(ctx, static_cast<float*>(U), nsteps, st);
+  return record_impl<double>(ctx, static_cast<double*>(U), nsteps, st);
+}
+
+int hydro_adjoint_recorded(hydro_ctx* ctx, void* lambda, double* grad_jets, void* stream) {
+  if (!ctx || !lambda) return fail(ctx, HYDRO_EINVAL, "bad arguments to hydro_adjoint_recorded");
+  if (ctx->njet > 0 && !grad_jets) return fail(ctx, HYDRO_EINVAL, "jets need grad_jets");
+  if (ctx->rec_n == 0)
+    return fail(ctx, HYDRO_ESTATE, "no recorded steps: hydro_rk3_step_record first (hydro_adjoint_step, "
+                                   "hydro_reset, hydro_set_state, hydro_add_jet and hydro_set_jet discard the record)");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  if (ctx->cfg.precision == HYDRO_F32)
+    return recorded_impl<float>(ctx, static_cast<float*>(lambda), grad_jets, st);
+  return recorded_impl<double>(ctx, static_cast<double*>(lambda), grad_jets, st);
 }
 
 int hydro_init_vjp(hydro_ctx* ctx, const double* prim0, const void* lambda, double* grad_prim, void* stream) {

@@ -32,6 +32,7 @@ EXPORTED = [
     "hydro_batch_rhs", "hydro_batch_set_option", "hydro_batch_get_option", "hydro_batch_autotune",
     "hydro_batch_sums", "hydro_batch_get_state", "hydro_batch_diag", "hydro_batch_last_error",
     "hydro_batch_destroy", "hydro_sums_noalloc", "hydro_freezeout", "hydro_step_sums",
+    "hydro_rk3_step_record", "hydro_adjoint_recorded",
 ]
 OPT_YZ_KERNEL, OPT_MARCH_SEG, OPT_X_KERNEL, OPT_ADJ_SKIP_N, OPT_TILE_ORDER, OPT_ADJ_LINES = 0, 1, 2, 3, 4, 5
 BOPT_BLOCKS_X, BOPT_BLOCKS_Y, BOPT_BLOCKS_Z, BOPT_GRAPH, BOPT_X_ROWS = 0, 1, 2, 3, 4
@@ -128,6 +129,8 @@ def load_library(path: str = LIB_PATH):
     lib.hydro_loss_eps2.argtypes = [vp, vp, vp, vp, ctypes.c_double, vp]
     lib.hydro_adjoint_step.argtypes = [vp, vp, ctypes.c_int64, dp, ctypes.c_int, vp, vp, vp]
     lib.hydro_init_vjp.argtypes = [vp, vp, vp, vp, vp]
+    lib.hydro_rk3_step_record.argtypes = [vp, vp, ctypes.c_int, vp]
+    lib.hydro_adjoint_recorded.argtypes = [vp, vp, vp, vp]
     lib.hydro_get_option.argtypes = [vp, ctypes.c_int, ctypes.POINTER(ctypes.c_int)]
     lib.hydro_profile_read.argtypes = [vp, dp, ctypes.POINTER(ctypes.c_int64), ctypes.c_int]
     lib.hydro_batch_workspace_bytes.argtypes = [cp, ctypes.c_int]
@@ -282,6 +285,18 @@ class Hydro:
         gp = grad_jets.data_ptr() if grad_jets is not None else None
         self._check(self.lib.hydro_adjoint_step(self.ctx, U_ckpt.data_ptr(), int(step0), E if self.njet else None,
                                                 int(nsteps), lam.data_ptr(), gp, _stream_handle(stream)))
+
+    def step_record(self, nsteps: int, stream=None):
+        """hydro_rk3_step_record: nsteps steps (as step) keeping their stage
+        states in the adjoint workspace for adjoint_recorded."""
+        self._check(self.lib.hydro_rk3_step_record(self.ctx, self.U.data_ptr(), int(nsteps), _stream_handle(stream)))
+
+    def adjoint_recorded(self, lam, grad_jets, stream=None):
+        """hydro_adjoint_recorded: reverse sweep over the recorded steps; lam
+        (like U) in: dJ/dU after them, out: before them; grad_jets (njet, 5)
+        float64 device tensor is incremented."""
+        gp = grad_jets.data_ptr() if grad_jets is not None else None
+        self._check(self.lib.hydro_adjoint_recorded(self.ctx, lam.data_ptr(), gp, _stream_handle(stream)))
 
     def init_vjp(self, prim0, lam, stream=None):
         """(dU/dprim)^T lam at prim0 (device float64) -> (5, nz, ny, nx) float64."""

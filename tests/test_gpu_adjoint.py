@@ -53,9 +53,9 @@ def oracle_jets(w):
     return [O.Jet(**j.__dict__) for j in w.jets]
 
 
-def gpu_grads(w, precision="f64", ckpt=2):
+def gpu_grads(w, precision="f64", ckpt=2, record=False):
     A = adjoint_mod()
-    pb = A.Eps2Problem(w, precision=precision, ckpt_every=ckpt)
+    pb = A.Eps2Problem(w, precision=precision, ckpt_every=ckpt, record=record)
     j = w.jets[0]
     e0 = torch.tensor(w.prim0[0], dtype=torch.float64, device="cuda")
     eps, cks, Uf, prim = pb.forward(e0, j.kappa_rad, j.kappa_coll, j.x0[0], j.x0[1])
@@ -559,3 +559,86 @@ def test_adjoint_sweep_leaves_the_fixup_count_alone():
     torch.cuda.synchronize()
     assert h.fixups() == f
     h.close()
+
+
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+@pytest.mark.parametrize("deposit", ["gauss", "ngp"])
+def test_recorded_stage_states_give_the_checkpointed_gradients(precision, deposit):
+    """hydro_rk3_step_record + hydro_adjoint_recorded (stage states kept
+    from the forward, no recompute) against checkpoints every 2 steps: eps2,
+    the initial-field and jet gradients bit for bit."""
+    w = small(steps=5, deposit=deposit)
+    print("recorded", precision, deposit, w.n, w.steps, flush=True)
+    a = gpu_grads(w, precision=precision, ckpt=2)
+    b = gpu_grads(w, precision=precision, record=True)
+    assert b["eps2"] == a["eps2"]
+    assert np.array_equal(b["jets"], a["jets"])
+    assert np.array_equal(b["e_init"], a["e_init"])
+
+
+def test_recorded_steps_equal_plain_steps_and_their_record_lifetime():
+    """The recording forward advances U, the step sums, the jet energies and
+    the ledger exactly as hydro_rk3_step; the record serves repeated sweeps
+    (the same result each time) and is discarded by hydro_set_jet,
+    hydro_reset, hydro_set_state and hydro_adjoint_step (HYDRO_ESTATE
+    after); a sweep leaves U, step, jet energies, ledger and fix-up count
+    alone; more steps than the workspace holds is HYDRO_EINVAL."""
+    from paper_1511_02137_amd import hydro as H
+    w = small(n=(16, 16, 16), steps=3)
+    a = H.from_workload(w, adjoint_k=3)
+    b = H.from_workload(w)
+    a.step_record(3)
+    b.step(3)
+    torch.cuda.synchronize()
+    assert torch.equal(a.U, b.U)
+    assert np.array_equal(a.step_sums(), b.step_sums())
+    sa, sb = a.get_state(), b.get_state()
+    assert sa[0] == sb[0] and sa[1] == sb[1] and np.array_equal(sa[2], sb[2])
+    assert a.sums()[5] == b.sums()[5]
+    U_end, state_end, f_end = a.U.clone(), a.get_state(), a.fixups()
+    lam0 = torch.empty_like(a.U)
+    a.loss_eps2(a.U, seed=lam0)
+    res = []
+    for _ in range(2):
+        lam = lam0.clone()
+        grad = torch.zeros((1, 5), dtype=torch.float64, device="cuda")
+        a.adjoint_recorded(lam, grad)
+        torch.cuda.synchronize()
+        res.append((lam, grad))
+    assert torch.equal(res[0][0], res[1][0]) and torch.equal(res[0][1], res[1][1])
+    assert torch.equal(a.U, U_end) and a.fixups() == f_end
+    st = a.get_state()
+    assert st[0] == state_end[0] and st[1] == state_end[1] and np.array_equal(st[2], state_end[2])
+    j = w.jets[0]
+    grad = torch.zeros((1, 5), dtype=torch.float64, device="cuda")
+    for discard in (lambda: a.set_jet(0, j.x0, j.dir, j.E0, j.t_start, j.kappa_rad, j.kappa_coll, j.cr_over_cf),
+                    lambda: a.reset(torch.from_numpy(w.prim0)),
+                    lambda: a.set_state(*a.get_state()[1:], 0.0),
+                    lambda: a.adjoint_step(U_end, 0, [j.E0], 1, lam0.clone(), grad)):
+        a.step_record(2)
+        discard()
+        with pytest.raises(H.HydroError) as ei:
+            a.adjoint_recorded(lam0.clone(), grad)
+        assert ei.value.code == H.HYDRO_ESTATE
+    with pytest.raises(H.HydroError) as ei:
+        a.step_record(4)
+    assert ei.value.code == H.HYDRO_EINVAL
+    a.close()
+    b.close()
+
+
+def test_recorded_problem_refuses_a_backward_after_another_forward():
+    """With the stage states kept from the forward, a backward belongs to the
+    latest forward: an earlier one's backward is refused, not silently
+    differentiated through the later run's states."""
+    A = adjoint_mod()
+    w = small(n=(16, 16, 16), steps=3)
+    pb = A.Eps2Problem(w, record=True)
+    j = w.jets[0]
+    e0 = torch.tensor(w.prim0[0], dtype=torch.float64, device="cuda")
+    fa = pb.forward(e0, j.kappa_rad, j.kappa_coll, j.x0[0], j.x0[1])
+    fb = pb.forward(e0, 2.0 * j.kappa_rad, j.kappa_coll, j.x0[0], j.x0[1])
+    with pytest.raises(RuntimeError):
+        pb.backward(fa[1], fa[2], fa[3])
+    pb.backward(fb[1], fb[2], fb[3])
+    pb.h.close()
