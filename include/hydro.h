@@ -160,8 +160,9 @@ void hydro_default_config(hydro_config* cfg);
  * two stage states and one flux-divergence field (15 words per cell) plus
  * reduction partials (conservation sums, eps2, freeze-out: 8 MiB).
  * adjoint_k > 0 adds room for the 3*adjoint_k stage
- * states one hydro_adjoint_step of adjoint_k steps recomputes and for the
- * adjoint fields.  Returns 0 for an invalid cfg. */
+ * states one hydro_adjoint_step of adjoint_k steps recomputes (or
+ * hydro_rk3_step_record of adjoint_k steps keeps) and for the adjoint
+ * fields.  Returns 0 for an invalid cfg. */
 size_t hydro_workspace_bytes(const hydro_config* cfg, int adjoint_k);
 
 /* Create a context and set U from primitive fields: the conserved variables
