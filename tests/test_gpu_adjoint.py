@@ -213,7 +213,16 @@ def test_adjoint_rejects_more_steps_than_workspace():
     h0 = H.from_workload(w)  # no adjoint workspace
     with pytest.raises(H.HydroError):
         h0.adjoint_step(h0.U.clone(), 0, [w.jets[0].E0], 1, torch.zeros_like(h0.U), grad)
+    with pytest.raises(H.HydroError) as ei:
+        h0.step_record(1)
+    assert ei.value.code == H.HYDRO_EINVAL
+    with pytest.raises(H.HydroError) as ei:  # nothing recorded
+        h0.adjoint_recorded(torch.zeros_like(h0.U), grad)
+    assert ei.value.code == H.HYDRO_ESTATE
     h0.close()
+    # schemes the adjoint does not cover get no adjoint workspace at all
+    with pytest.raises(H.HydroError):
+        H.from_workload(w, weno="z5", adjoint_k=2)
 
 
 # --- the differentiable run's sizes --------------------------------------------------------------------------------
