@@ -651,3 +651,27 @@ def test_recorded_problem_refuses_a_backward_after_another_forward():
         pb.backward(fa[1], fa[2], fa[3])
     pb.backward(fb[1], fb[2], fb[3])
     pb.h.close()
+
+
+def test_recorded_problem_under_autograd():
+    """eps2(...) through torch.autograd with the stage states kept from the
+    forward: the value and every gradient equal those of the checkpointed
+    problem bit for bit."""
+    A = adjoint_mod()
+    w = small(n=(16, 16, 16), steps=3)
+    j = w.jets[0]
+
+    def run(pb):
+        e0 = torch.tensor(w.prim0[0], dtype=torch.float64, device="cuda", requires_grad=True)
+        p = [torch.tensor(v, dtype=torch.float64, requires_grad=True)
+             for v in (j.kappa_rad, j.kappa_coll, list(j.x0[:2]))]
+        e = A.eps2(e0, *p, pb)
+        g = torch.autograd.grad(e, [e0, *p])
+        pb.h.close()
+        return float(e), g
+
+    ec, gc = run(A.Eps2Problem(w, ckpt_every=2))
+    er, gr = run(A.Eps2Problem(w, record=True))
+    assert er == ec
+    for a, b in zip(gr, gc):
+        assert torch.equal(a.cpu(), b.cpu())
