@@ -377,6 +377,30 @@ def batch_throughput(precision: str, steps: int, warmup: int, cache, limiter: st
     return out
 
 
+def log_run(h, steps: int, path: str) -> int:
+    """Steps h one at a time and appends one JSON line per step to path: the
+    step's FP64 sums (hydro_step_sums), ledger, jet energies, fix-up count and
+    per-kernel-class times (HIP events); each step sits in a roctx range
+    ("hydro step <n>") for rocprofv3's marker trace.  Untimed diagnostics, not
+    a benchmark.  Returns the number of lines written."""
+    import torch
+    h.profile(True)
+    with open(path, "a") as f:
+        for _ in range(steps):
+            n = h.get_state()[1]
+            torch.cuda.nvtx.range_push("hydro step %d" % n)
+            h.step(1)
+            torch.cuda.nvtx.range_pop()
+            ss = h.step_sums()
+            t, step, Ej = h.get_state()
+            prof = h.profile_read()
+            f.write(json.dumps({"step": step, "t": t, "sums": [float(v) for v in ss[:5]], "ledger": float(ss[5]),
+                                "E_jet": [float(v) for v in Ej], "fixups": h.fixups(),
+                                "kernels_ms": {k: ms for k, (ms, c) in prof.items() if c}}) + "\n")
+    h.profile(False)
+    return steps
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -412,6 +436,9 @@ def main():
     ap.add_argument("--tune-cache", default=None, help="autotuner cache file of the ensemble run")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain device copy of 1 GiB 10 times (scale for the HBM counters)")
+    ap.add_argument("--log", default=None,
+                    help="only run --steps steps of the stage workload one at a time, appending one JSON line "
+                         "per step (sums, ledger, jet energies, fix-ups, kernel times) to this file")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -442,6 +469,11 @@ def main():
     h.set_option(H.OPT_X_KERNEL, 0 if args.x == "row" else 1)
     h.set_option(H.OPT_TILE_ORDER, args.tile_order)
     nc = w.n[0] * w.n[1] * w.n[2]
+    if args.log:
+        log_run(h, args.steps, args.log)
+        h.close()
+        print("logged %d steps of %s to %s" % (args.steps, w.name, args.log), file=sys.stderr)
+        return
 
     h.step(args.warmup)
     torch.cuda.synchronize()

@@ -586,3 +586,28 @@ def test_jet_parameter_checks():
     h.close()
     ref.close()
     b.close()
+
+
+def test_step_log(tmp_path):
+    """bench.py's per-step log (one JSON line per step): the sums and ledger
+    are those of a plain run's steps bit for bit, the jet loses what the
+    ledger gains, and every line carries the step's kernel times."""
+    import json
+    import bench
+    w = W.small_event(1, n=(24, 20, 18), steps=4)
+    h = H().from_workload(w)
+    path = tmp_path / "log.jsonl"
+    assert bench.log_run(h, 4, str(path)) == 4
+    recs = [json.loads(line) for line in path.read_text().splitlines()]
+    assert [r["step"] for r in recs] == [1, 2, 3, 4]
+    ref = H().from_workload(w)
+    for r in recs:
+        ref.step(1)
+        ss = ref.step_sums()
+        assert r["sums"] == [float(v) for v in ss[:5]] and r["ledger"] == float(ss[5])
+        assert r["fixups"] == 0 and r["kernels_ms"]["xface"] > 0.0
+    last = recs[-1]
+    assert last["ledger"] > 0.0
+    assert abs((w.jets[0].E0 - last["E_jet"][0]) - last["ledger"]) <= 1e-12 * w.jets[0].E0
+    h.close()
+    ref.close()
