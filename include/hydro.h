@@ -465,7 +465,9 @@ int hydro_batch_get_option(hydro_batch* b, int option, long long* value);
  * Synchronous. */
 int hydro_batch_autotune(hydro_batch* b, const char* cache_path, void* stream, int* from_cache);
 
-/* Synchronous: sums of event `event` as hydro_sums (ledger in out[5]). */
+/* Synchronous: sums of event `event` taken by the last batch step, as
+ * hydro_sums (ledger in out[5]; HYDRO_ENONPHYS, out still written, when a
+ * sum is not finite or, in strict mode, after a fix-up of that event). */
 int hydro_batch_sums(hydro_batch* b, int event, double out[6]);
 
 /* Synchronous: time, step and the remaining jet energies of one event. */

@@ -545,9 +545,15 @@ int hydro_batch_sums(hydro_batch* b, int event, double out[6]) {
   if (!b || !out || event < 0 || event >= b->n) return bfail(b, HYDRO_EINVAL, "bad arguments to hydro_batch_sums");
   hipError_t e = hipDeviceSynchronize();
   DevScalars* s = b->d_dev + event;
+  unsigned long long fix = 0;
   if (e == hipSuccess) e = hipMemcpy(out, s->sums, 5 * sizeof(double), hipMemcpyDeviceToHost);
   if (e == hipSuccess) e = hipMemcpy(out + 5, &s->ledger, sizeof(double), hipMemcpyDeviceToHost);
+  if (e == hipSuccess) e = hipMemcpy(&fix, &s->fixups, sizeof(fix), hipMemcpyDeviceToHost);
   if (e != hipSuccess) return bhip(b, e, "hydro_batch_sums");
+  // as hydro_sums: non-finite sums, and fix-ups in strict mode, are reported
+  for (int c = 0; c < 6; ++c)
+    if (!std::isfinite(out[c])) return bfail(b, HYDRO_ENONPHYS, "non-finite sums (NaN or infinity in the event's state)");
+  if (b->cfg[event].strict && fix > 0) return bfail(b, HYDRO_ENONPHYS, "non-admissible cells of the event were fixed up");
   return HYDRO_OK;
 }
 

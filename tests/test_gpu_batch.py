@@ -211,3 +211,29 @@ def test_full_ensemble_matches_single_events():
     assert_batch_equals_single(b, ws, 2, "f32")
     assert b.fixups() == 0
     b.close()
+
+
+def test_batch_sums_report_non_finite_sums_and_strict_fixups():
+    """hydro_batch_sums reports as hydro_sums: a NaN in one event's state
+    makes that event's sums HYDRO_ENONPHYS and leaves the other's alone; in
+    strict mode an event whose non-admissible cell was fixed up is
+    HYDRO_ENONPHYS, the other event is not."""
+    w0 = W.small_event(1, n=(16, 16, 16), with_jet=False)
+    w1 = W.small_event(2, n=(16, 16, 16), with_jet=False)
+    b = H().batch_from_workloads([w0, w1], precision="f64")
+    b.U[1][0, 8, 8, 8] = float("nan")
+    b.run(1)
+    assert np.all(np.isfinite(b.sums(0)))
+    with pytest.raises(H().HydroError) as ei:
+        b.sums(1)
+    assert ei.value.code == H().HYDRO_ENONPHYS
+    b.close()
+    cfgs = [H().make_config(w.n, precision="f64", strict=True) for w in (w0, w1)]
+    bs = H().Batch(cfgs, [w0.prim0, w1.prim0])
+    bs.U[0][0, 3, 3, 3] = -1.0
+    bs.run(1)
+    with pytest.raises(H().HydroError) as ei:
+        bs.sums(0)
+    assert ei.value.code == H().HYDRO_ENONPHYS
+    assert np.all(np.isfinite(bs.sums(1)))
+    bs.close()
