@@ -414,9 +414,14 @@ class Hydro:
         return {KERNELS[k]: (ms[k], n[k]) for k in range(nk)}
 
     def close(self):
+        """Destroys the context and releases its workspace (the library no
+        longer uses it)."""
         if getattr(self, "ctx", None):
+            import torch
             self.lib.hydro_destroy(self.ctx)
             self.ctx = None
+            torch.cuda.synchronize(self.device)  # no launch of the context still reads it
+            self.ws = None
 
     def __del__(self):
         try:
