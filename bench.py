@@ -196,9 +196,11 @@ ADJ_FLOPS_RECON = 155 + 122
 
 def adjoint_ratio(precision: str, n: int, steps: int, ckpt: int, repeats: int = 3):
     """Differentiable run (workloads.gradient_event): forward = reset, the
-    steps with a checkpoint every `ckpt` steps, eps2; backward = loss seed,
-    reverse sweep over every segment (recomputing its stage states), initial
-    state VJP.  Best of `repeats` after one untimed pass, GPU-synchronised."""
+    steps with a checkpoint every `ckpt` steps (the last segment's stage
+    states kept as it runs), eps2; backward = loss seed, reverse sweep over
+    every segment (recomputing the stage states of all but the last),
+    initial state VJP.  Best of `repeats` after one untimed pass,
+    GPU-synchronised."""
     import torch
     from paper_1511_02137_amd import adjoint as A
     from paper_1511_02137_amd import workloads as W
@@ -219,6 +221,7 @@ def adjoint_ratio(precision: str, n: int, steps: int, ckpt: int, repeats: int = 
         if r:
             tf.append(t1 - t0)
             tb.append(t2 - t1)
+    eps, cks, Uf, prim = pb.forward(e0, j.kappa_rad, j.kappa_coll, j.x0[0], j.x0[1])
     pb.h.profile(True)
     pb.backward(cks, Uf, prim)
     torch.cuda.synchronize()

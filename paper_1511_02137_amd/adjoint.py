@@ -7,10 +7,13 @@ inputs are kappa_rad, kappa_coll of jet 0 (the energy-loss law, Eq. 3) and
 its origin (x0, y0).
 
 Forward: hydro_reset from the primitives, the steps (a checkpoint of U and of
-the jet energies every `ckpt_every` steps), hydro_loss_eps2.  Backward: the
-loss seed, hydro_adjoint_step over each segment in reverse (each segment's
-stage states are recomputed from its checkpoint), then hydro_init_vjp for
-d/de_init.  Every step runs in libhydro's kernels; this module orders the
+the jet energies every `ckpt_every` steps; the last segment's stage states
+are kept as it runs, hydro_rk3_step_record), hydro_loss_eps2.  Backward: the
+loss seed, the reverse sweep over each segment from the last (the last one
+from its kept stage states, hydro_adjoint_recorded, while the workspace still
+holds them; the others, and the last one after anything replaced them, by
+hydro_adjoint_step, which recomputes them from the segment's checkpoint:
+bit for bit the same), then hydro_init_vjp for d/de_init.  Every step runs in libhydro's kernels; this module orders the
 calls and keeps the checkpoints (torch tensors in HBM).
 """
 from __future__ import annotations
@@ -28,6 +31,7 @@ class Checkpoint:
     U: object            # torch tensor like Hydro.U
     step: int
     E_jet: np.ndarray
+    recorded: int = 0    # forward whose recorded stage states cover this segment (0: none)
 
 
 @dataclass
@@ -55,6 +59,8 @@ class Eps2Problem:
         self.record = bool(record)
         self.k = self.steps if self.record else int(ckpt_every)
         self._generation = 0
+        self._params = None   # the jet parameters the context holds
+        self._live = 0        # forward whose recorded stage states the workspace still holds (0: none)
         self.h = H.from_workload(workload, precision=precision, adjoint_k=self.k, device=device)
         # eps2 depends on e and v only, so the adjoint of N is zero throughout
         self.h.set_option(H.OPT_ADJ_SKIP_N, 1)
@@ -64,6 +70,8 @@ class Eps2Problem:
     def set_params(self, kappa_rad: float, kappa_coll: float, x0: float, y0: float):
         j = self.jet
         self.h.set_jet(0, (x0, y0, j.x0[2]), j.dir, j.E0, j.t_start, kappa_rad, kappa_coll, j.cr_over_cf)
+        self._params = (float(kappa_rad), float(kappa_coll), float(x0), float(y0))
+        self._live = 0  # hydro_set_jet discards a record
 
     def forward(self, e_init, kappa_rad: float, kappa_coll: float, x0: float, y0: float):
         """Runs the steps; returns (eps2 device scalar, checkpoints, final U, primitives)."""
@@ -75,13 +83,22 @@ class Eps2Problem:
             self.h.step_record(self.steps)
             self._generation += 1
             return self.h.loss_eps2(), [Recorded(self._generation)], self.h.U.clone(), prim
+        # the last segment's stage states are kept as it runs, so that the
+        # backward sweeps it without a recompute while they are still there
+        self._generation += 1
+        self._live = 0
         cks: List[Checkpoint] = []
         s = 0
         while s < self.steps:
             _, step, Ej = self.h.get_state()
             cks.append(Checkpoint(self.h.U.clone(), step, Ej))
             n = min(self.k, self.steps - s)
-            self.h.step(n)
+            if s + n == self.steps:
+                self.h.step_record(n)
+                cks[-1].recorded = self._generation
+                self._live = self._generation
+            else:
+                self.h.step(n)
             s += n
         eps = self.h.loss_eps2()
         return eps, cks, self.h.U.clone(), prim
@@ -98,7 +115,7 @@ class Eps2Problem:
             if len(cks) != 1 or not isinstance(cks[0], Recorded) or cks[0].generation != self._generation:
                 raise RuntimeError("another forward replaced the recorded stage states of this one "
                                    "(record=False keeps checkpoints and allows interleaved forwards)")
-        elif params is not None:
+        elif params is not None and tuple(float(v) for v in params) != self._params:
             self.set_params(*params)
         lam = torch.empty_like(U_final)
         self.h.loss_eps2(U_final, seed=lam, scale=scale)
@@ -108,7 +125,11 @@ class Eps2Problem:
         else:
             ends = [c.step for c in cks[1:]] + [self.steps]
             for ck, end in reversed(list(zip(cks, ends))):
-                self.h.adjoint_step(ck.U, ck.step, ck.E_jet, end - ck.step, lam, grad)
+                if ck.recorded and ck.recorded == self._live:
+                    self.h.adjoint_recorded(lam, grad)
+                else:
+                    self.h.adjoint_step(ck.U, ck.step, ck.E_jet, end - ck.step, lam, grad)
+                    self._live = 0  # the recompute overwrote the record
         gprim = self.h.init_vjp(prim, lam)
         return gprim[0], grad
 

@@ -675,3 +675,23 @@ def test_recorded_problem_under_autograd():
     assert er == ec
     for a, b in zip(gr, gc):
         assert torch.equal(a.cpu(), b.cpu())
+
+
+def test_checkpointed_backward_with_and_without_the_kept_last_segment():
+    """The checkpointed forward keeps its last segment's stage states; the
+    first backward sweeps that segment from them, a second backward of the
+    same forward (the record overwritten by the first one's recomputes)
+    recomputes every segment: the same gradients bit for bit."""
+    A = adjoint_mod()
+    w = small(steps=5)
+    pb = A.Eps2Problem(w, ckpt_every=2)
+    j = w.jets[0]
+    e0 = torch.tensor(w.prim0[0], dtype=torch.float64, device="cuda")
+    eps, cks, Uf, prim = pb.forward(e0, j.kappa_rad, j.kappa_coll, j.x0[0], j.x0[1])
+    assert [c.recorded != 0 for c in cks] == [False, False, True]
+    g1 = pb.backward(cks, Uf, prim)
+    assert pb._live == 0
+    g2 = pb.backward(cks, Uf, prim)
+    torch.cuda.synchronize()
+    assert torch.equal(g1[0], g2[0]) and torch.equal(g1[1], g2[1])
+    pb.h.close()
